@@ -1,0 +1,102 @@
+"""IMEX multistep slice propagators and Fourier resampling (oracle).
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+
+The explicit operator (advection/stretching, curl(u x b)) is stepped
+explicitly and the diffusion Rm^-1 (lap - kz^2) = -|k|^2/Rm implicitly
+(Section 4: explicit (u.grad)B and (B.grad)u, implicit diffusion).  The
+stepper is the second-order semi-implicit backward difference formula SBDF2
+of the multistep IMEX family Section 4 cites.  Because a multistep method
+must restart in every time slice (Section 4), each slice starts with one
+SBDF1 (backward/forward Euler) step:
+
+  SBDF1:  (1 + dt|k|^2/Rm) b1 = b0 + dt N(b0, t0)
+  SBDF2:  (3/2 + dt|k|^2/Rm) b_{j+1} = 2 b_j - b_{j-1}/2
+                                       + dt (2 N(b_j, t_j) - N(b_{j-1}, t_{j-1}))
+
+with t_j = t0 + j dt evaluated as a product, never accumulated.
+
+Coarse grids (Section 3.2, "reduced spatial resolution, along with a larger
+time step"; Section 4, Fourier re-sampling between the two solvers): a field
+moves to an N_C grid by keeping the coefficients inside the N_C 2/3 box, and
+back by zero padding.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import spectral as sp
+
+
+def propagate(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
+              dt: float, nsteps: int) -> np.ndarray:
+    """Advance one field ``[3][N][N]`` by ``nsteps`` steps of size ``dt``
+    from time ``t0``: one SBDF1 start step, then SBDF2."""
+    if nsteps < 1:
+        raise ValueError("nsteps must be >= 1")
+    N = bh.shape[-1]
+    a = dt * sp.k_squared(N, kz) / Rm
+    b_old = np.array(bh, dtype=np.complex128)
+    n_old = sp.explicit_term(b_old, flow, kz, t0)
+    b = (b_old + dt * n_old) / (1.0 + a)
+    for j in range(1, nsteps):
+        n_j = sp.explicit_term(b, flow, kz, t0 + j * dt)
+        b_new = (2.0 * b - 0.5 * b_old + dt * (2.0 * n_j - n_old)) / (1.5 + a)
+        b_old, b, n_old = b, b_new, n_j
+    return b
+
+
+def restrict(bh: np.ndarray, Nc: int) -> np.ndarray:
+    """Fine ``[3][N][N]`` -> coarse ``[3][Nc][Nc]``: keep the modes with
+    |kx|, |ky| <= floor((Nc - 1)/3), drop the rest."""
+    N = bh.shape[-1]
+    if Nc == N:
+        return np.array(bh, dtype=np.complex128)
+    Kc = sp.box_K(Nc)
+    kc = sp.wavenumbers(Nc)
+    out = np.zeros(bh.shape[:-2] + (Nc, Nc), dtype=np.complex128)
+    for iy in range(Nc):
+        for ix in range(Nc):
+            ky, kx = int(kc[iy]), int(kc[ix])
+            if abs(ky) <= Kc and abs(kx) <= Kc:
+                out[..., iy, ix] = bh[..., ky % N, kx % N]
+    return out
+
+
+def prolong(bc: np.ndarray, N: int) -> np.ndarray:
+    """Coarse ``[3][Nc][Nc]`` -> fine ``[3][N][N]`` by zero padding."""
+    Nc = bc.shape[-1]
+    if Nc == N:
+        return np.array(bc, dtype=np.complex128)
+    kc = sp.wavenumbers(Nc)
+    out = np.zeros(bc.shape[:-2] + (N, N), dtype=np.complex128)
+    for iy in range(Nc):
+        for ix in range(Nc):
+            ky, kx = int(kc[iy]), int(kc[ix])
+            out[..., ky % N, kx % N] = bc[..., iy, ix]
+    return out
+
+
+class SliceSolver:
+    """One propagator (F or G) over a Parareal time slice [t_n, t_n + dT].
+
+    ``N_solver`` is the grid it steps on; fields come in and go out on the
+    fine grid ``N`` (restricted on entry, prolonged on exit when the grids
+    differ, Section 4 pseudo-code: set_scales before and after the coarse
+    solve).
+    """
+
+    def __init__(self, flow: str, Rm: float, kz: float, N: int, dT: float,
+                 dt: float, N_solver: int | None = None):
+        steps = dT / dt
+        n = int(round(steps))
+        if n < 1 or abs(steps - n) > 1e-9 * max(1.0, steps):
+            raise ValueError("slice length must be an integer number of steps")
+        self.flow, self.Rm, self.kz, self.N = flow, Rm, kz, N
+        self.dT, self.dt, self.nsteps = dT, dt, n
+        self.N_solver = N if N_solver is None else N_solver
+
+    def __call__(self, bh: np.ndarray, t0: float) -> np.ndarray:
+        x = restrict(bh, self.N_solver)
+        y = propagate(x, self.flow, self.Rm, self.kz, t0, self.dt, self.nsteps)
+        return prolong(y, self.N)
