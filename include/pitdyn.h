@@ -1,0 +1,154 @@
+/*
+ * pitdyn -- Parareal for 2.5D kinematic dynamos on AMD Instinct MI355X.
+ *
+ * C ABI of libpitdyn.so.  The library integrates the dimensionless induction
+ * equation dB/dt = curl(u x B) + Rm^-1 lap B (Clarke, Davies, Ruprecht &
+ * Tobias, arXiv:1902.00387, Section 1, eq. induction-dimensionless-1) for
+ * B = b(x, y, t) exp(i kz z) on the 2pi-periodic square (Section 1, 2.5D
+ * ansatz; Section 4, Fourier collocation with N x N modes), with a prescribed
+ * flow (Section 2: Roberts flow, Section 2.1; Galloway-Proctor CP flow,
+ * Section 2.2), and runs the Parareal iteration of Section 3
+ * (eq. parareal) with the defect of eq. error.
+ *
+ * Field layout ("full layout"): complex128 coefficients as interleaved
+ * (re, im) doubles, [nfields][3][N][N] = [field][component x,y,z][ky index]
+ * [kx index], index m standing for wavenumber m if m < N/2 else m - N, so that
+ * b(x, y) = sum_k b_k exp(i (kx x + ky y)).  Every coefficient outside the
+ * square 2/3 box |kx|, |ky| <= floor((N - 1)/3) must be zero (dealiasing
+ * rule); a nonzero one is rejected with PD_EINVAL.
+ *
+ * Time stepping: explicit curl(u x b), implicit diffusion -|k|^2/Rm
+ * (Section 4), by the second-order semi-implicit backward difference
+ * formula (SBDF2) started in every slice with one SBDF1 step (Section 4:
+ * multistep methods restart in every slice).  Coarse propagator: same
+ * scheme on an N_C grid with step dt_coarse (Section 3.2 "reduced spatial
+ * resolution, along with a larger time step"; Section 4 Fourier
+ * re-sampling between the grids).
+ *
+ * Conventions for every call:
+ *  - returns a pd_status; no C++ exception crosses the ABI;
+ *    pd_last_error(ctx) gives a message for the last failure on ctx;
+ *  - host pointers are read or written only during the call, caller owned;
+ *  - device pointers ("_dev") are borrowed for the call; work is queued on
+ *    the given HIP stream (hipStream_t passed as void*, NULL = the context's
+ *    stream) and the call returns after the work completes on that stream;
+ *  - a context is not thread safe; use one per host thread.
+ */
+#ifndef PITDYN_H
+#define PITDYN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_ctx pd_ctx;
+
+typedef enum {
+  PD_OK = 0,
+  PD_NOT_CONVERGED = 1, /* Parareal stopped at max_iter with sigma > tol  */
+  PD_EINVAL = -1,       /* invalid argument or field outside the 2/3 box  */
+  PD_ENOMEM = -2,       /* device allocation failed                       */
+  PD_EHIP = -3,         /* HIP runtime error (message in pd_last_error)   */
+  PD_ESTATE = -4,       /* call out of order (e.g. no problem set)        */
+  PD_EUNSTABLE = -5     /* non-finite state (unstable step size)          */
+} pd_status;
+
+typedef enum {
+  PD_FLOW_NONE = 0,    /* u = 0: pure diffusion                           */
+  PD_FLOW_ROBERTS = 1, /* u = (cos y, sin x, sin y + cos x), Section 2.1 */
+  PD_FLOW_GP = 2       /* Galloway-Proctor CP flow, Section 2.2, with the  */
+                       /* paper's (y, z, x) relabelled as (x, y, z):       */
+                       /* u = A (cos(y + sin t), sin(x + cos t),           */
+                       /*        cos(x + cos t) + sin(y + sin t)),         */
+                       /* A = sqrt(3/2), t absolute time                   */
+} pd_flow;
+
+typedef enum {
+  PD_PATH_AUTO = -1,   /* library chooses                                 */
+  PD_PATH_MULTI = 0,   /* two launches per step over all fields and tiles */
+  PD_PATH_SINGLE = 1   /* one workgroup per field runs every step         */
+} pd_path;
+
+#define PD_MAX_ITER 256
+
+typedef struct {
+  int k_con;                   /* first k with sigma_k <= tol, -1 if none  */
+  int iters;                   /* Parareal iterations run (fine sweeps)    */
+  double sigma[PD_MAX_ITER];   /* sigma_k, k = 1..iters (eq. error)        */
+  double t_coarse0_s;          /* initial coarse run (GPU time)            */
+  double t_fine_s;             /* all fine sweeps (GPU time)               */
+  double t_coarse_s;           /* all correction sweeps (GPU time)         */
+  double t_total_s;            /* wall clock of the whole call             */
+} pd_report;
+
+/* Context on HIP device `hip_device` with its own stream. */
+pd_status pd_create(pd_ctx** out, int hip_device);
+void pd_destroy(pd_ctx* ctx);
+/* Message of the last failure on ctx ("" if none); valid until the next call. */
+const char* pd_last_error(const pd_ctx* ctx);
+/* Queue subsequent work of pd_parareal / host-pointer calls on this stream
+   (borrowed; NULL restores the context's own stream). */
+pd_status pd_set_stream(pd_ctx* ctx, void* hip_stream);
+
+/* Problem: flow, Rm > 0, kz (any real), N in {16, 32, 64, 128, 256, 512}
+   (Section 4: N x N Fourier modes).  Frees slice buffers of an earlier problem. */
+pd_status pd_set_problem(pd_ctx* ctx, pd_flow flow, double Rm, double kz, int N);
+
+/* Parareal time grid (Section 3): [0, T] cut into n_slices slices of length
+   dT = T/n_slices; fine step dt_fine, coarse step dt_coarse on an N_coarse
+   grid (0 = same as N, else a power of two in [16, N]).  dT/dt_fine and
+   dT/dt_coarse must be integers to 1e-9 relative.  Allocates the slice buffers
+   ((4 n_slices + 2) fields of 3 (2K+1)^2 complex values plus 2 n_slices row
+   buffers of 3 (2K+1) N values). */
+pd_status pd_set_time(pd_ctx* ctx, double T, int n_slices, double dt_fine, double dt_coarse,
+                      int N_coarse);
+
+/* Choose how batched fine propagation is launched (testing and tuning). */
+pd_status pd_set_path(pd_ctx* ctx, pd_path path);
+
+/* Initial field U_0, full layout [3][N][N], host or device memory. */
+pd_status pd_set_initial(pd_ctx* ctx, const double* b0);
+pd_status pd_set_initial_dev(pd_ctx* ctx, const void* d_b0, void* hip_stream);
+
+/* Fine propagator F over one slice for `batch` independent fields:
+   out[f] = F(in[f]) from time t0[f] (host array) to t0[f] + dT with dt_fine
+   (n_f = dT/dt_fine steps, Section 3 "fine method").  in and out: device,
+   full layout [batch][3][N][N]; they may alias.  Needs pd_set_time. */
+pd_status pd_fine_dev(pd_ctx* ctx, const double* t0, int batch, const void* d_in, void* d_out,
+                      void* hip_stream);
+/* Coarse propagator G over one slice: restrict to the N_coarse box, n_c =
+   dT/dt_coarse steps on the N_coarse grid, zero-pad back (Section 4,
+   set_scales re-sampling).  Same arguments as pd_fine_dev. */
+pd_status pd_coarse_dev(pd_ctx* ctx, const double* t0, int batch, const void* d_in, void* d_out,
+                        void* hip_stream);
+/* Any number of steps of size dt on the fine grid from t0[f] (no slice
+   length needed): out = n_steps SBDF steps (first one SBDF1). */
+pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int n_steps,
+                       const void* d_in, void* d_out, void* hip_stream);
+
+/* Parareal (Section 3): initial coarse run, then iterations
+   U^k_{n+1} = F(U^{k-1}_n) + (G(U^k_n) - G(U^{k-1}_n)) until
+   sigma_k = |U^k_P - U^{k-1}_P|_2 / |U^k_P|_2 <= tol or k = max_iter
+   (max_iter <= PD_MAX_ITER; tol = 0 runs exactly max_iter iterations).  Slices
+   already converged (n < k - 1 in iteration k) are not recomputed: their
+   results are unchanged bitwise.  `rep` may be NULL.  Returns PD_OK,
+   PD_NOT_CONVERGED, or PD_EUNSTABLE if a defect sum is not finite. */
+pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
+
+/* Slice-boundary states U_n, n = 0..n_slices, full layout [P+1][3][N][N]. */
+pd_status pd_get_slices(const pd_ctx* ctx, double* out);
+pd_status pd_get_slices_dev(const pd_ctx* ctx, void* d_out, void* hip_stream);
+
+/* |U_n|_2 for n = 0..n_slices (host array of n_slices + 1 doubles). */
+pd_status pd_slice_norms(const pd_ctx* ctx, double* norms);
+/* Amplitude growth rate: least-squares slope of ln|U_n|_2 against t_n over
+   n = ceil(P/2) .. P of the current iterate (the paper's Table 1 reports
+   growth rates without naming an estimator; this is the reading used). */
+pd_status pd_growth_rate(const pd_ctx* ctx, double* gamma);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PITDYN_H */

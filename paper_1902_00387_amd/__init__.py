@@ -1,0 +1,239 @@
+"""Python binding of libpitdyn.so (Parareal for 2.5D kinematic dynamos on
+MI355X).  Argument marshalling only: every numerical step runs in the HIP
+library; PyTorch supplies device memory and streams.
+
+Fields are complex128 arrays ``[..., 3, N, N]`` of Fourier coefficients
+(component, ky index, kx index; index m is wavenumber m if m < N/2 else
+m - N), zero outside the 2/3 box |kx|, |ky| <= (N-1)//3.  See
+``include/pitdyn.h`` for the C-ABI this wraps.
+
+Importing this package loads the library and raises if it is missing: there
+is no CPU fallback.  torch is imported first so that the process holds one
+HIP runtime (torch's): the library resolves ``libamdhip64.so.7`` to the copy
+already loaded, and torch tensors, streams and the library share a context.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading the library, see above)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpitdyn.so")
+
+FLOW_NONE, FLOW_ROBERTS, FLOW_GP = 0, 1, 2
+FLOWS = {"none": FLOW_NONE, "roberts": FLOW_ROBERTS, "gp": FLOW_GP}
+PATH_AUTO, PATH_MULTI, PATH_SINGLE = -1, 0, 1
+MAX_ITER = 256
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, EUNSTABLE = 0, 1, -1, -2, -3, -4, -5
+
+# every symbol include/pitdyn.h declares
+SYMBOLS = [
+    "pd_create", "pd_destroy", "pd_last_error", "pd_set_stream", "pd_set_problem",
+    "pd_set_time", "pd_set_path", "pd_set_initial", "pd_set_initial_dev", "pd_fine_dev",
+    "pd_coarse_dev", "pd_steps_dev", "pd_parareal", "pd_get_slices", "pd_get_slices_dev",
+    "pd_slice_norms", "pd_growth_rate",
+]
+
+
+class Report(C.Structure):
+    _fields_ = [
+        ("k_con", C.c_int),
+        ("iters", C.c_int),
+        ("sigma", C.c_double * MAX_ITER),
+        ("t_coarse0_s", C.c_double),
+        ("t_fine_s", C.c_double),
+        ("t_coarse_s", C.c_double),
+        ("t_total_s", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {
+            "k_con": self.k_con, "iters": self.iters,
+            "sigma": [self.sigma[i] for i in range(self.iters)],
+            "t_coarse0_s": self.t_coarse0_s, "t_fine_s": self.t_fine_s,
+            "t_coarse_s": self.t_coarse_s, "t_total_s": self.t_total_s,
+        }
+
+
+class PitdynError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pitdyn status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python paper_1902_00387_amd/build.py` "
+            "(hipcc, gfx950); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "pd_create": ([C.POINTER(vp), i], i),
+        "pd_destroy": ([vp], None),
+        "pd_last_error": ([vp], C.c_char_p),
+        "pd_set_stream": ([vp, vp], i),
+        "pd_set_problem": ([vp, i, d, d, i], i),
+        "pd_set_time": ([vp, d, i, d, d, i], i),
+        "pd_set_path": ([vp, i], i),
+        "pd_set_initial": ([vp, dp], i),
+        "pd_set_initial_dev": ([vp, vp, vp], i),
+        "pd_fine_dev": ([vp, dp, i, vp, vp, vp], i),
+        "pd_coarse_dev": ([vp, dp, i, vp, vp, vp], i),
+        "pd_steps_dev": ([vp, dp, i, d, i, vp, vp, vp], i),
+        "pd_parareal": ([vp, d, i, C.POINTER(Report)], i),
+        "pd_get_slices": ([vp, dp], i),
+        "pd_get_slices_dev": ([vp, vp, vp], i),
+        "pd_slice_norms": ([vp, dp], i),
+        "pd_growth_rate": ([vp, dp], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(x, N):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if x.dtype != torch.complex128 or not x.is_contiguous():
+        raise TypeError("expected a contiguous complex128 tensor")
+    if x.shape[-3:] != (3, N, N):
+        raise ValueError(f"expected shape [..., 3, {N}, {N}], got {tuple(x.shape)}")
+
+
+class Context:
+    """One pitdyn context (device memory, stream, problem, slice buffers)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = lib.pd_create(C.byref(h), device)
+        if st != OK:
+            raise PitdynError(st, "pd_create failed")
+        self._h = h
+        self.N = None
+        self.P = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _ok(self, st, allow=(OK,)):
+        if st not in allow:
+            raise PitdynError(st, lib.pd_last_error(self._h).decode())
+        return st
+
+    # -- problem set-up -----------------------------------------------------
+    def set_problem(self, flow, Rm: float, kz: float, N: int):
+        f = FLOWS[flow] if isinstance(flow, str) else int(flow)
+        self._ok(lib.pd_set_problem(self._h, f, float(Rm), float(kz), int(N)))
+        self.N = int(N)
+
+    def set_time(self, T: float, n_slices: int, dt_fine: float, dt_coarse: float, N_coarse: int = 0):
+        self._ok(lib.pd_set_time(self._h, float(T), int(n_slices), float(dt_fine),
+                                 float(dt_coarse), int(N_coarse)))
+        self.P = int(n_slices)
+
+    def set_path(self, path: int):
+        self._ok(lib.pd_set_path(self._h, int(path)))
+
+    def set_stream(self, stream_handle):
+        self._ok(lib.pd_set_stream(self._h, C.c_void_p(stream_handle)))
+
+    def set_initial(self, b0):
+        import torch
+        if isinstance(b0, torch.Tensor) and b0.is_cuda:
+            _check_dev(b0, self.N)
+            self._ok(lib.pd_set_initial_dev(self._h, C.c_void_p(b0.data_ptr()), _stream()))
+        else:
+            a = np.ascontiguousarray(np.asarray(b0, dtype=np.complex128))
+            if a.shape != (3, self.N, self.N):
+                raise ValueError(f"initial field must be [3, {self.N}, {self.N}]")
+            self._ok(lib.pd_set_initial(self._h, _dptr(a.view(np.float64))))
+
+    # -- propagators on device tensors --------------------------------------
+    def _prop(self, fn, t0, x, out, *extra):
+        import torch
+        _check_dev(x, self.N)
+        xb = x.reshape(-1, 3, self.N, self.N)
+        if out is None:
+            out = torch.empty_like(xb)
+        _check_dev(out, self.N)
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, np.float64), (xb.shape[0],)))
+        self._ok(fn(self._h, _dptr(t), xb.shape[0], *extra, C.c_void_p(xb.data_ptr()),
+                    C.c_void_p(out.data_ptr()), _stream()))
+        return out.reshape(x.shape)
+
+    def fine(self, t0, x, out=None):
+        """F over one slice for every field of x ([..., 3, N, N], device)."""
+        return self._prop(lib.pd_fine_dev, t0, x, out)
+
+    def coarse(self, t0, x, out=None):
+        """G over one slice (restrict, coarse steps, zero-pad)."""
+        return self._prop(lib.pd_coarse_dev, t0, x, out)
+
+    def steps(self, t0, dt: float, n_steps: int, x, out=None):
+        """n_steps SBDF steps of size dt on the fine grid."""
+        return self._prop(lib.pd_steps_dev, t0, x, out, C.c_double(dt), C.c_int(n_steps))
+
+    # -- Parareal -----------------------------------------------------------
+    def parareal(self, tol: float, max_iter: int):
+        rep = Report()
+        st = self._ok(lib.pd_parareal(self._h, float(tol), int(max_iter), C.byref(rep)),
+                      allow=(OK, NOT_CONVERGED))
+        d = rep.as_dict()
+        d["status"] = st
+        return d
+
+    def get_slices(self) -> np.ndarray:
+        out = np.empty((self.P + 1, 3, self.N, self.N), np.complex128)
+        self._ok(lib.pd_get_slices(self._h, _dptr(out.view(np.float64))))
+        return out
+
+    def get_slices_dev(self):
+        import torch
+        out = torch.empty((self.P + 1, 3, self.N, self.N), dtype=torch.complex128, device="cuda")
+        self._ok(lib.pd_get_slices_dev(self._h, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def slice_norms(self) -> np.ndarray:
+        out = np.empty(self.P + 1, np.float64)
+        self._ok(lib.pd_slice_norms(self._h, _dptr(out)))
+        return out
+
+    def growth_rate(self) -> float:
+        g = C.c_double()
+        self._ok(lib.pd_growth_rate(self._h, C.byref(g)))
+        return g.value

@@ -1,0 +1,611 @@
+// C-ABI runtime of libpitdyn.so: contexts, device buffers, the Parareal
+// driver (Section 3 of Clarke et al., arXiv:1902.00387) and the propagator
+// entry points.  Every step of the numerical path runs in the HIP kernels of
+// kernels.hip; this file only validates arguments, owns memory and orders
+// launches on a stream.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pitdyn.h"
+#include "launch.hpp"
+
+using pd::cplx;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, n ? n : 16);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = n;
+    return hipSuccess;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+int box_K(int N) { return (N - 1) / 3; }
+int box_M(int N) { return 2 * box_K(N) + 1; }
+bool valid_N(int N) {
+  return N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512;
+}
+
+// e^{-2 pi i m/N}, m = 0..N-1.  Angles are reduced to the first octant and
+// evaluated in extended precision, so quadrant values are exact and the
+// table is symmetric to the last bit.
+std::vector<cplx> twiddles(int N) {
+  std::vector<cplx> tw(N);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  const int n4 = N / 4;
+  for (int m = 0; m < N; ++m) {
+    const int q = m / n4, r = m % n4;
+    long double c, s;
+    if (2 * r <= n4) {
+      const long double a = two_pi * (long double)r / (long double)N;
+      c = cosl(a);
+      s = sinl(a);
+    } else {
+      const long double a = two_pi * (long double)(n4 - r) / (long double)N;
+      c = sinl(a);
+      s = cosl(a);
+    }
+    long double cq, sq;  // rotate by q quarter turns
+    switch (q) {
+      case 0: cq = c; sq = s; break;
+      case 1: cq = -s; sq = c; break;
+      case 2: cq = -c; sq = -s; break;
+      default: cq = s; sq = -c; break;
+    }
+    tw[m] = {(double)cq, (double)(-sq)};
+  }
+  return tw;
+}
+
+bool integer_ratio(double a, double b, int* n) {
+  if (!(a > 0) || !(b > 0)) return false;
+  const double q = a / b;
+  const double r = std::nearbyint(q);
+  if (r < 1 || r > 1e9 || std::fabs(q - r) > 1e-9 * r) return false;
+  *n = (int)r;
+  return true;
+}
+
+}  // namespace
+
+struct pd_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int path = PD_PATH_AUTO;
+  // problem
+  bool have_problem = false;
+  int flow = PD_FLOW_NONE;
+  double Rm = 1, kz = 0;
+  int N = 0, K = 0, M = 0;
+  // time grid
+  bool have_time = false;
+  double T = 0, dT = 0, dtf = 0, dtc = 0;
+  int P = 0, Nc = 0, Mc = 0, nf = 0, nc = 0;
+  bool have_initial = false;
+  // device memory
+  DevBuf tw, twc;                      // twiddles (fine, coarse)
+  DevBuf U, Fo, Gold, Hf, T1f, T2f;    // slice buffers
+  DevBuf Uprev, t0s;                   // defect copy, slice start times
+  DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
+  DevBuf red, flag;                    // reduction outputs, box-check flag
+  DevBuf wB, wH, wT1, wT2, wt0;        // workspaces of the propagator calls
+  double* hred = nullptr;              // pinned host copy of red
+
+  size_t box_elems() const { return (size_t)3 * M * M; }
+  size_t rows_elems() const { return (size_t)3 * M * N; }
+};
+
+namespace {
+
+pd_status fail(pd_ctx* c, pd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+pd_status hipfail(pd_ctx* c, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(c, PD_ENOMEM, "%s: out of device memory", what);
+  return fail(c, PD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PD_HIP(ctx, expr, what)                       \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hipfail(ctx, e_, what); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(d);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+pd::Problem make_problem(const pd_ctx* c, double dt) {
+  pd::Problem pb;
+  pb.Rm = c->Rm;
+  pb.kz = c->kz;
+  pb.dt = dt;
+  pb.amp = c->flow == PD_FLOW_NONE ? 0.0 : (c->flow == PD_FLOW_ROBERTS ? 1.0 : std::sqrt(1.5));
+  pb.tdep = c->flow == PD_FLOW_GP ? 1 : 0;
+  return pb;
+}
+
+int choose_path(const pd_ctx* c, int nfields) {
+  if (c->path == PD_PATH_MULTI || c->path == PD_PATH_SINGLE) return c->path;
+  return nfields >= 512 ? pd::PATH_SINGLE_WG : pd::PATH_MULTI;
+}
+
+// Validate `nfields` full-layout device fields: zero outside the 2/3 box.
+pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStream_t st) {
+  PD_HIP(c, c->flag.ensure(sizeof(int)), "alloc");
+  PD_HIP(c, hipMemsetAsync(c->flag.p, 0, sizeof(int), st), "memset");
+  PD_HIP(c, pd::check_box(static_cast<const cplx*>(d), N, nfields, c->flag.as<int>(), st),
+         "check_box");
+  int h = 0;
+  PD_HIP(c, hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  if (h) return fail(c, PD_EINVAL, "input field has nonzero coefficients outside the 2/3 box");
+  return PD_OK;
+}
+
+// Propagate `batch` full-layout fields by nsteps steps of dt on grid N (with
+// restriction to Ngrid <= N and zero-padding back when Ngrid < N).
+pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
+                         int Ngrid, const void* d_in, void* d_out, hipStream_t st) {
+  if (!c->have_problem) return fail(c, PD_ESTATE, "pd_set_problem not called");
+  if (batch < 0 || batch > 65535) return fail(c, PD_EINVAL, "batch must be in [0, 65535]");
+  if (batch == 0) return PD_OK;
+  if (!t0 || !d_in || !d_out) return fail(c, PD_EINVAL, "null pointer argument");
+  if (nsteps < 1) return fail(c, PD_EINVAL, "n_steps must be >= 1");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(c, PD_EINVAL, "dt must be positive");
+  for (int f = 0; f < batch; ++f)
+    if (!std::isfinite(t0[f])) return fail(c, PD_EINVAL, "t0 must be finite");
+  DeviceGuard dg(c->device);
+  pd_status s = check_box_dev(c, d_in, c->N, batch, st);
+  if (s != PD_OK) return s;
+  const int Mg = box_M(Ngrid);
+  const size_t box = (size_t)3 * Mg * Mg, rows = (size_t)3 * Mg * Ngrid;
+  PD_HIP(c, c->wB.ensure(box * batch * sizeof(cplx)), "alloc");
+  PD_HIP(c, c->wH.ensure(box * batch * sizeof(cplx)), "alloc");
+  PD_HIP(c, c->wT1.ensure(rows * batch * sizeof(cplx)), "alloc");
+  PD_HIP(c, c->wT2.ensure(rows * batch * sizeof(cplx)), "alloc");
+  PD_HIP(c, c->wt0.ensure(sizeof(double) * batch), "alloc");
+  PD_HIP(c, hipMemcpyAsync(c->wt0.p, t0, sizeof(double) * batch, hipMemcpyHostToDevice, st),
+         "copy t0");
+  DevBuf* twb = &c->tw;
+  if (Ngrid != c->N) {
+    std::vector<cplx> tw = twiddles(Ngrid);
+    PD_HIP(c, c->twc.ensure(sizeof(cplx) * Ngrid), "alloc");
+    PD_HIP(c, hipMemcpyAsync(c->twc.p, tw.data(), sizeof(cplx) * Ngrid, hipMemcpyHostToDevice, st),
+           "copy tw");
+    PD_HIP(c, hipStreamSynchronize(st), "sync");
+    twb = &c->twc;
+  }
+  // full layout on N -> compact box of Ngrid: for Ngrid < N the pack keeps
+  // only |k| <= Kg (restriction) and the unpack zero-pads (prolongation)
+  PD_HIP(c, pd::pack(static_cast<const cplx*>(d_in), c->wB.as<cplx>(), c->N, Mg, (size_t)batch, st),
+         "pack");
+  pd::FieldBatch fb;
+  fb.B = c->wB.as<cplx>();
+  fb.H = c->wH.as<cplx>();
+  fb.T1 = c->wT1.as<cplx>();
+  fb.T2 = c->wT2.as<cplx>();
+  fb.t0 = c->wt0.as<double>();
+  fb.tw = twb->as<cplx>();
+  const pd::Problem pb = make_problem(c, dt);
+  PD_HIP(c, pd::propagate(Ngrid, fb, pb, batch, nsteps, choose_path(c, batch), st), "propagate");
+  PD_HIP(c, pd::unpack(c->wB.as<cplx>(), static_cast<cplx*>(d_out), c->N, Mg, (size_t)batch, st),
+         "unpack");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pd_status pd_create(pd_ctx** out, int hip_device) {
+  if (!out) return PD_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return PD_EINVAL;
+  pd_ctx* c = new (std::nothrow) pd_ctx;
+  if (!c) return PD_ENOMEM;
+  c->device = hip_device;
+  DeviceGuard dg(hip_device);
+  if (hipStreamCreate(&c->own) != hipSuccess || hipHostMalloc((void**)&c->hred, 4 * sizeof(double)) != hipSuccess) {
+    delete c;
+    return PD_EHIP;
+  }
+  c->stream = c->own;
+  *out = c;
+  return PD_OK;
+}
+
+void pd_destroy(pd_ctx* c) {
+  if (!c) return;
+  {
+    DeviceGuard dg(c->device);
+    if (c->own) {
+      (void)hipStreamSynchronize(c->own);
+      (void)hipStreamDestroy(c->own);
+    }
+    if (c->hred) (void)hipHostFree(c->hred);
+    c->tw.release(); c->twc.release(); c->U.release(); c->Fo.release(); c->Gold.release();
+    c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
+    c->Bc.release(); c->Hc.release(); c->T1c.release(); c->T2c.release(); c->red.release();
+    c->flag.release(); c->wB.release(); c->wH.release(); c->wT1.release(); c->wT2.release();
+    c->wt0.release();
+  }
+  delete c;
+}
+
+const char* pd_last_error(const pd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pd_status pd_set_stream(pd_ctx* c, void* s) {
+  if (!c) return PD_EINVAL;
+  c->stream = s ? static_cast<hipStream_t>(s) : c->own;
+  return PD_OK;
+}
+
+pd_status pd_set_path(pd_ctx* c, pd_path p) {
+  if (!c) return PD_EINVAL;
+  if (p != PD_PATH_AUTO && p != PD_PATH_MULTI && p != PD_PATH_SINGLE)
+    return fail(c, PD_EINVAL, "unknown path %d", (int)p);
+  c->path = p;
+  return PD_OK;
+}
+
+pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (flow != PD_FLOW_NONE && flow != PD_FLOW_ROBERTS && flow != PD_FLOW_GP)
+    return fail(c, PD_EINVAL, "unknown flow %d", (int)flow);
+  if (!(Rm > 0) || !std::isfinite(Rm)) return fail(c, PD_EINVAL, "Rm must be positive");
+  if (!std::isfinite(kz)) return fail(c, PD_EINVAL, "kz must be finite");
+  if (!valid_N(N)) return fail(c, PD_EINVAL, "N must be one of 16, 32, 64, 128, 256, 512");
+  DeviceGuard dg(c->device);
+  c->have_problem = c->have_time = c->have_initial = false;
+  c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
+  c->T2f.release(); c->Uprev.release();
+  c->flow = flow;
+  c->Rm = Rm;
+  c->kz = kz;
+  c->N = N;
+  c->K = box_K(N);
+  c->M = box_M(N);
+  std::vector<cplx> tw = twiddles(N);
+  PD_HIP(c, c->tw.ensure(sizeof(cplx) * N), "alloc twiddles");
+  PD_HIP(c, hipMemcpy(c->tw.p, tw.data(), sizeof(cplx) * N, hipMemcpyHostToDevice), "copy");
+  c->have_problem = true;
+  return PD_OK;
+}
+
+pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_problem) return fail(c, PD_ESTATE, "pd_set_problem not called");
+  if (!(T > 0) || !std::isfinite(T)) return fail(c, PD_EINVAL, "T must be positive");
+  if (P < 1 || P > 65535) return fail(c, PD_EINVAL, "n_slices must be in [1, 65535]");
+  if (Nc == 0) Nc = c->N;
+  if (!valid_N(Nc) || Nc > c->N) return fail(c, PD_EINVAL, "N_coarse must be a power of two in [16, N]");
+  const double dT = T / P;
+  int nf = 0, nc = 0;
+  if (!integer_ratio(dT, dtf, &nf)) return fail(c, PD_EINVAL, "slice length is not an integer number of fine steps");
+  if (!integer_ratio(dT, dtc, &nc)) return fail(c, PD_EINVAL, "slice length is not an integer number of coarse steps");
+  DeviceGuard dg(c->device);
+  c->have_time = c->have_initial = false;
+  c->T = T; c->P = P; c->dT = dT; c->dtf = dtf; c->dtc = dtc; c->Nc = Nc; c->Mc = box_M(Nc);
+  c->nf = nf; c->nc = nc;
+  const size_t box = c->box_elems() * sizeof(cplx), rows = c->rows_elems() * sizeof(cplx);
+  const size_t cbox = (size_t)3 * c->Mc * c->Mc * sizeof(cplx), crows = (size_t)3 * c->Mc * Nc * sizeof(cplx);
+  PD_HIP(c, c->U.ensure(box * (P + 1)), "alloc U");
+  PD_HIP(c, c->Fo.ensure(box * P), "alloc F");
+  PD_HIP(c, c->Gold.ensure(box * P), "alloc Gold");
+  PD_HIP(c, c->Hf.ensure(box * P), "alloc H");
+  PD_HIP(c, c->T1f.ensure(rows * P), "alloc T1");
+  PD_HIP(c, c->T2f.ensure(rows * P), "alloc T2");
+  PD_HIP(c, c->Uprev.ensure(box), "alloc");
+  PD_HIP(c, c->Bc.ensure(cbox), "alloc");
+  PD_HIP(c, c->Hc.ensure(cbox), "alloc");
+  PD_HIP(c, c->T1c.ensure(crows), "alloc");
+  PD_HIP(c, c->T2c.ensure(crows), "alloc");
+  PD_HIP(c, c->red.ensure(4 * sizeof(double)), "alloc");
+  PD_HIP(c, c->t0s.ensure(sizeof(double) * P), "alloc");
+  std::vector<double> t0(P);
+  for (int n = 0; n < P; ++n) t0[n] = n * dT;
+  PD_HIP(c, hipMemcpy(c->t0s.p, t0.data(), sizeof(double) * P, hipMemcpyHostToDevice), "copy");
+  std::vector<cplx> twc = twiddles(Nc);
+  PD_HIP(c, c->twc.ensure(sizeof(cplx) * Nc), "alloc");
+  PD_HIP(c, hipMemcpy(c->twc.p, twc.data(), sizeof(cplx) * Nc, hipMemcpyHostToDevice), "copy");
+  PD_HIP(c, hipMemset(c->U.p, 0, box * (P + 1)), "memset");
+  c->have_time = true;
+  return PD_OK;
+}
+
+pd_status pd_set_initial_dev(pd_ctx* c, const void* d_b0, void* s) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (!d_b0) return fail(c, PD_EINVAL, "null pointer argument");
+  DeviceGuard dg(c->device);
+  hipStream_t st = static_cast<hipStream_t>(s);
+  pd_status r = check_box_dev(c, d_b0, c->N, 1, st);
+  if (r != PD_OK) return r;
+  PD_HIP(c, pd::pack(static_cast<const cplx*>(d_b0), c->U.as<cplx>(), c->N, c->M, 1, st), "pack");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  c->have_initial = true;
+  return PD_OK;
+}
+
+pd_status pd_set_initial(pd_ctx* c, const double* b0) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (!b0) return fail(c, PD_EINVAL, "null pointer argument");
+  const int N = c->N, K = c->K;
+  for (int comp = 0; comp < 3; ++comp)
+    for (int my = 0; my < N; ++my)
+      for (int mx = 0; mx < N; ++mx) {
+        const int ky = my < N / 2 ? my : my - N, kx = mx < N / 2 ? mx : mx - N;
+        const size_t i = 2 * (((size_t)comp * N + my) * N + mx);
+        if ((ky < -K || ky > K || kx < -K || kx > K) && (b0[i] != 0.0 || b0[i + 1] != 0.0))
+          return fail(c, PD_EINVAL, "initial field has nonzero coefficients outside the 2/3 box");
+      }
+  DeviceGuard dg(c->device);
+  DevBuf tmp;
+  const size_t bytes = (size_t)3 * N * N * sizeof(cplx);
+  PD_HIP(c, tmp.ensure(bytes), "alloc");
+  PD_HIP(c, hipMemcpyAsync(tmp.p, b0, bytes, hipMemcpyHostToDevice, c->stream), "copy");
+  PD_HIP(c, pd::pack(tmp.as<cplx>(), c->U.as<cplx>(), N, c->M, 1, c->stream), "pack");
+  PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  c->have_initial = true;
+  return PD_OK;
+}
+
+pd_status pd_steps_dev(pd_ctx* c, const double* t0, int batch, double dt, int n_steps,
+                       const void* d_in, void* d_out, void* s) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  return run_propagator(c, t0, batch, dt, n_steps, c->N, d_in, d_out, static_cast<hipStream_t>(s));
+}
+
+pd_status pd_fine_dev(pd_ctx* c, const double* t0, int batch, const void* d_in, void* d_out,
+                      void* s) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  return run_propagator(c, t0, batch, c->dtf, c->nf, c->N, d_in, d_out, static_cast<hipStream_t>(s));
+}
+
+pd_status pd_coarse_dev(pd_ctx* c, const double* t0, int batch, const void* d_in, void* d_out,
+                        void* s) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  return run_propagator(c, t0, batch, c->dtc, c->nc, c->Nc, d_in, d_out, static_cast<hipStream_t>(s));
+}
+
+pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_initial) return fail(c, PD_ESTATE, "pd_set_initial not called");
+  if (max_iter < 0 || max_iter > PD_MAX_ITER) return fail(c, PD_EINVAL, "max_iter must be in [0, %d]", PD_MAX_ITER);
+  if (!(tol >= 0)) return fail(c, PD_EINVAL, "tol must be >= 0");
+  DeviceGuard dg(c->device);
+  const auto wall0 = std::chrono::steady_clock::now();
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems(), rows = c->rows_elems();
+  const int P = c->P;
+  cplx* U = c->U.as<cplx>();
+  cplx* Fo = c->Fo.as<cplx>();
+  pd_report r;
+  std::memset(&r, 0, sizeof r);
+  r.k_con = -1;
+  hipEvent_t ev[4];
+  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); }
+  } evf{ev};
+
+  pd::SweepArgs sa;
+  sa.U = U;
+  sa.Fo = Fo;
+  sa.Gold = c->Gold.as<cplx>();
+  sa.Uprev = c->Uprev.as<cplx>();
+  sa.Bc = c->Bc.as<cplx>();
+  sa.Hc = c->Hc.as<cplx>();
+  sa.T1c = c->T1c.as<cplx>();
+  sa.T2c = c->T2c.as<cplx>();
+  sa.twc = c->twc.as<cplx>();
+  sa.red = c->red.as<double>();
+  sa.dT = c->dT;
+  sa.M = c->M;
+  sa.P = P;
+  sa.nsteps = c->nc;
+  const pd::Problem pc = make_problem(c, c->dtc), pf = make_problem(c, c->dtf);
+
+  // initial coarse run (Section 3: U^0_n from G over [0, T])
+  sa.n0 = 0;
+  sa.mode = 0;
+  PD_HIP(c, hipEventRecord(ev[0], st), "event");
+  PD_HIP(c, pd::sweep(c->Nc, sa, pc, st), "coarse sweep");
+  PD_HIP(c, hipEventRecord(ev[1], st), "event");
+  PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+  float ms = 0;
+  PD_HIP(c, hipEventElapsedTime(&ms, ev[0], ev[1]), "event");
+  r.t_coarse0_s = ms * 1e-3;
+
+  pd_status status = PD_NOT_CONVERGED;
+  for (int k = 1; k <= max_iter; ++k) {
+    const int n0 = k - 1 < P - 1 ? k - 1 : P - 1;
+    PD_HIP(c, hipMemcpyAsync(c->Uprev.p, U + (size_t)P * box, box * sizeof(cplx),
+                             hipMemcpyDeviceToDevice, st), "copy");
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    // fine sweep over the slices whose start value can still change
+    PD_HIP(c, hipMemcpyAsync(Fo + (size_t)n0 * box, U + (size_t)n0 * box,
+                             (size_t)(P - n0) * box * sizeof(cplx), hipMemcpyDeviceToDevice, st),
+           "copy");
+    pd::FieldBatch fb;
+    fb.B = Fo + (size_t)n0 * box;
+    fb.H = c->Hf.as<cplx>() + (size_t)n0 * box;
+    fb.T1 = c->T1f.as<cplx>() + (size_t)n0 * rows;
+    fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
+    fb.t0 = c->t0s.as<double>() + n0;
+    fb.tw = c->tw.as<cplx>();
+    PD_HIP(c, pd::propagate(c->N, fb, pf, P - n0, c->nf, choose_path(c, P - n0), st), "fine sweep");
+    PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    // serial coarse sweep with the correction, then the defect sums
+    sa.n0 = n0;
+    sa.mode = 1;
+    PD_HIP(c, pd::sweep(c->Nc, sa, pc, st), "coarse sweep");
+    PD_HIP(c, hipEventRecord(ev[2], st), "event");
+    PD_HIP(c, hipMemcpyAsync(c->hred, c->red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    PD_HIP(c, hipStreamSynchronize(st), "sync");
+    float mf = 0, mc = 0;
+    PD_HIP(c, hipEventElapsedTime(&mf, ev[0], ev[1]), "event");
+    PD_HIP(c, hipEventElapsedTime(&mc, ev[1], ev[2]), "event");
+    r.t_fine_s += mf * 1e-3;
+    r.t_coarse_s += mc * 1e-3;
+    const double num = c->hred[0], den = c->hred[1];
+    r.iters = k;
+    if (!std::isfinite(num) || !std::isfinite(den)) {
+      status = fail(c, PD_EUNSTABLE, "non-finite state at iteration %d (unstable step size?)", k);
+      break;
+    }
+    const double sigma = den > 0 ? std::sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+    r.sigma[k - 1] = sigma;
+    if (sigma <= tol) {
+      r.k_con = k;
+      status = PD_OK;
+      break;
+    }
+  }
+  if (max_iter == 0) status = PD_OK;
+  r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  if (rep) *rep = r;
+  return status;
+}
+
+pd_status pd_get_slices_dev(const pd_ctx* cc, void* d_out, void* s) {
+  pd_ctx* c = const_cast<pd_ctx*>(cc);
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (!d_out) return fail(c, PD_EINVAL, "null pointer argument");
+  DeviceGuard dg(c->device);
+  hipStream_t st = static_cast<hipStream_t>(s);
+  PD_HIP(c, pd::unpack(c->U.as<cplx>(), static_cast<cplx*>(d_out), c->N, c->M, (size_t)c->P + 1, st), "unpack");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  return PD_OK;
+}
+
+pd_status pd_get_slices(const pd_ctx* cc, double* out) {
+  pd_ctx* c = const_cast<pd_ctx*>(cc);
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (!out) return fail(c, PD_EINVAL, "null pointer argument");
+  DeviceGuard dg(c->device);
+  const size_t full = (size_t)3 * c->N * c->N;
+  DevBuf tmp;
+  PD_HIP(c, tmp.ensure(full * sizeof(cplx)), "alloc");
+  for (int n = 0; n <= c->P; ++n) {
+    PD_HIP(c, pd::unpack(c->U.as<cplx>() + (size_t)n * c->box_elems(), tmp.as<cplx>(), c->N, c->M, 1, c->stream), "unpack");
+    PD_HIP(c, hipMemcpyAsync(out + 2 * full * n, tmp.p, full * sizeof(cplx), hipMemcpyDeviceToHost, c->stream), "copy");
+  }
+  PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  return PD_OK;
+}
+
+pd_status pd_slice_norms(const pd_ctx* cc, double* norms) {
+  pd_ctx* c = const_cast<pd_ctx*>(cc);
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (!norms) return fail(c, PD_EINVAL, "null pointer argument");
+  DeviceGuard dg(c->device);
+  DevBuf d;
+  PD_HIP(c, d.ensure(sizeof(double) * (c->P + 1)), "alloc");
+  PD_HIP(c, pd::norms2(c->U.as<cplx>(), c->box_elems(), c->P + 1, d.as<double>(), c->stream), "norms");
+  PD_HIP(c, hipMemcpyAsync(norms, d.p, sizeof(double) * (c->P + 1), hipMemcpyDeviceToHost, c->stream), "copy");
+  PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  for (int n = 0; n <= c->P; ++n) norms[n] = std::sqrt(norms[n]);
+  return PD_OK;
+}
+
+pd_status pd_growth_rate(const pd_ctx* cc, double* gamma) {
+  pd_ctx* c = const_cast<pd_ctx*>(cc);
+  if (!c) return PD_EINVAL;
+  if (!gamma) return fail(c, PD_EINVAL, "null pointer argument");
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (c->P < 2) return fail(c, PD_EINVAL, "growth rate needs at least 2 slices");
+  std::vector<double> nrm(c->P + 1);
+  pd_status s = pd_slice_norms(c, nrm.data());
+  if (s != PD_OK) return s;
+  const int n0 = (c->P + 1) / 2;
+  const int cnt = c->P + 1 - n0;
+  double tm = 0, ym = 0;
+  std::vector<double> y(cnt), t(cnt);
+  for (int i = 0; i < cnt; ++i) {
+    if (!(nrm[n0 + i] > 0) || !std::isfinite(nrm[n0 + i]))
+      return fail(c, PD_EUNSTABLE, "slice norm is zero or not finite");
+    t[i] = (n0 + i) * c->dT;
+    y[i] = std::log(nrm[n0 + i]);
+    tm += t[i];
+    ym += y[i];
+  }
+  tm /= cnt;
+  ym /= cnt;
+  double sxy = 0, sxx = 0;
+  for (int i = 0; i < cnt; ++i) {
+    sxy += (t[i] - tm) * (y[i] - ym);
+    sxx += (t[i] - tm) * (t[i] - tm);
+  }
+  *gamma = sxy / sxx;
+  return PD_OK;
+}
+
+}  // extern "C"
