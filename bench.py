@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: Parareal for the Galloway-Proctor kinematic dynamo on one MI355X.
+
+Workload (one "step" = one whole Parareal solve, every stage of the path):
+  Galloway-Proctor CP flow, Rm = 100, kz = 0.57, 128 x 128 Fourier grid,
+  complex128, T = 64 cut into 64 slices; fine SBDF2 with dt = 2e-3 (500 steps a
+  slice, all 64 slices batched in every fine sweep); coarse SBDF2 on a 64 x 64
+  grid with dt = 1e-2 (the paper's N_C = N_F/2 with the largest stable step;
+  dt = 2e-2 blows up on 64 x 64); initial coarse run, Parareal iterations to a
+  defect sigma <= 1e-8, growth rate.  Seeded synthetic initial field.
+
+value: serial-equivalent fine mode-steps per second of the whole solve,
+  N^2 * slices * (steps per slice) / (time per solve) -- the rate at which the
+  solve delivers the serial fine solution.  Inputs are resident in HBM before
+  the timed region.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, KZ, RM, T, P = 128, 0.57, 100.0, 64.0, 64
+DT_FINE, DT_COARSE, N_COARSE = 2e-3, 1e-2, 64
+TOL, MAX_ITER, SEED = 1e-8, 64, 200000
+HBM_PEAK_GBS = 8000.0
+
+
+def box_m(n):
+    return 2 * ((n - 1) // 3) + 1
+
+
+def kernel_bytes(n, fields):
+    """Algorithmic HBM bytes of one launch of each phase kernel (complex128):
+    column phase reads T1 and writes T2 (3 M N values each); row phase reads
+    T2, reads and writes state and history (3 M^2 each) and writes T1."""
+    m = box_m(n)
+    cols = fields * 2 * 3 * m * n * 16
+    rows = fields * (2 * 3 * m * n + 4 * 3 * m * m) * 16
+    return cols, rows
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle's fine propagator on a bounded sample of the workload:
+    whole slices (500 steps at 128^2) one after another until the budget is
+    spent; NumPy's FFT and array arithmetic run on one thread."""
+    from oracle import stepper
+    from synthetic import initial_field
+    F = stepper.SliceSolver("gp", RM, KZ, N, T / P, DT_FINE)
+    b = initial_field(N, KZ, SEED)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        b = F(b, float(n))
+        n += 1
+        if time.perf_counter() - t0 >= budget_s or n >= P:
+            break
+    dt = time.perf_counter() - t0
+    steps = n * F.nsteps
+    return {"value": steps * N * N / dt, "unit": "fine mode-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n} of {P} slices x {F.nsteps} fine steps at {N}^2 "
+                      f"(serial, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the fine-sweep kernels (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
+              "path here is single-GPU; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    b0 = torch.from_numpy(initial_field(N, KZ, SEED)).to(dev)
+    ctx = pd.Context(0)
+    ctx.set_problem("gp", RM, KZ, N)
+    ctx.set_time(T, P, DT_FINE, DT_COARSE, N_COARSE)
+    nf = int(round(T / P / DT_FINE))
+
+    def solve():
+        ctx.set_initial(b0)
+        rep = ctx.parareal(TOL, MAX_ITER)
+        gam = ctx.growth_rate()
+        return rep, gam
+
+    if args.kernel_only:
+        ctx.set_initial(b0)
+        ctx.parareal(0.0, 0)
+        for _ in range(max(1, args.steps)):
+            ctx.profile_fine(20)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": True}), flush=True)
+        return
+
+    for _ in range(args.warmup):
+        rep, gam = solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep, gam = solve()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    serial_equiv = N * N * P * nf
+    value = serial_equiv / (ms_step * 1e-3)
+    print(f"# solve: k_con={rep['k_con']} sigma={rep['sigma'][-1]:.2e} gamma={gam:.6f} "
+          f"{ms_step:.1f} ms/solve (fine {rep['t_fine_s']*1e3:.1f} ms, coarse "
+          f"{(rep['t_coarse_s'] + rep['t_coarse0_s'])*1e3:.1f} ms)", file=sys.stderr, flush=True)
+
+    # kernel durations on the context's stream (HIP events), fine sweep rate
+    ctx.set_initial(b0)
+    ctx.parareal(0.0, 0)
+    ms_cols, ms_rows, ms_fstep = ctx.profile_fine(20)
+    cols_b, rows_b = kernel_bytes(N, P)
+    dominant = ("cols", ms_cols, cols_b) if ms_cols >= ms_rows else ("rows", ms_rows, rows_b)
+    achieved = dominant[2] / (dominant[1] * 1e-3) / 1e9
+    fine_rate = N * N * P / (ms_fstep * 1e-3)
+    alg_per_mode = (cols_b + rows_b) / (N * N * P)
+
+    # serial fine solve on the same GPU (slices one after another, batch 1)
+    u = b0[None].clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for n in range(P):
+        u = ctx.fine([n * T / P], u)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - ts
+
+    out = {
+        "metric": "fine-propagator mode-steps/sec (Parareal solve to sigma<=1e-8, serial-equivalent)",
+        "value": value,
+        "unit": "mode-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic (seeded Gaussian solenoidal initial field, |k|<=4, amplitude 1e-3)",
+        "config": {
+            "workload": "Galloway-Proctor kinematic dynamo Parareal, Rm=100, kz=0.57, 128x128, "
+                        "T=64 over 64 slices, fine SBDF2 dt=2e-3, coarse SBDF2 dt=1e-2 on 64x64, "
+                        "tol 1e-8",
+            "N": N, "slices": P, "fine_steps_per_slice": nf, "N_coarse": N_COARSE,
+            "dt_fine": DT_FINE, "dt_coarse": DT_COARSE, "tol": TOL,
+        },
+        "parareal": {
+            "k_con": rep["k_con"], "sigma": rep["sigma"], "growth_rate": gam,
+            "time_to_tol_s": ms_step * 1e-3,
+            "fine_sweeps_s": rep["t_fine_s"],
+            "coarse_sweeps_s": rep["t_coarse_s"] + rep["t_coarse0_s"],
+            "serial_fine_gpu_s": serial_s,
+            "speedup_vs_serial_fine_gpu": serial_s / (ms_step * 1e-3),
+        },
+        "fine_sweep": {
+            "mode_steps_per_s": fine_rate,
+            "ms_per_fine_step_all_slices": ms_fstep,
+            "ms_cols_kernel": ms_cols, "ms_rows_kernel": ms_rows,
+            "algorithmic_bytes_per_mode_step": alg_per_mode,
+            "algorithmic_hbm_gbs": alg_per_mode * fine_rate / 1e9,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_cols<128>" if dominant[0] == "cols" else "k_rows<128>",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

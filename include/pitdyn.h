@@ -30,8 +30,9 @@
  *    pd_last_error(ctx) gives a message for the last failure on ctx;
  *  - host pointers are read or written only during the call, caller owned;
  *  - device pointers ("_dev") are borrowed for the call; work is queued on
- *    the given HIP stream (hipStream_t passed as void*, NULL = the context's
+ *    the given HIP stream (hipStream_t passed as void*; NULL is HIP's null
  *    stream) and the call returns after the work completes on that stream;
+ *    calls without a stream argument use the context's stream;
  *  - a context is not thread safe; use one per host thread.
  */
 #ifndef PITDYN_H
@@ -136,6 +137,15 @@ pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int 
    results are unchanged bitwise.  `rep` may be NULL.  Returns PD_OK,
    PD_NOT_CONVERGED, or PD_EUNSTABLE if a defect sum is not finite. */
 pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
+
+/* Measurement helper: times the fine propagator on the context's slice
+   buffers (inputs: the current slice states U_0..U_{P-1}; the results are
+   discarded and U is left unchanged).  ms[2] = mean time per fine step of
+   one whole fine sweep over all slices as pd_parareal launches it; on the
+   multi-launch path ms[0] / ms[1] = mean duration of the column-phase /
+   row-phase (SBDF2) kernel over `reps` back-to-back launches on the
+   context's stream (0 on the single-workgroup path).  HIP events. */
+pd_status pd_profile_fine(pd_ctx* ctx, int reps, double* ms);
 
 /* Slice-boundary states U_n, n = 0..n_slices, full layout [P+1][3][N][N]. */
 pd_status pd_get_slices(const pd_ctx* ctx, double* out);

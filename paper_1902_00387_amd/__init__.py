@@ -35,7 +35,7 @@ SYMBOLS = [
     "pd_create", "pd_destroy", "pd_last_error", "pd_set_stream", "pd_set_problem",
     "pd_set_time", "pd_set_path", "pd_set_initial", "pd_set_initial_dev", "pd_fine_dev",
     "pd_coarse_dev", "pd_steps_dev", "pd_parareal", "pd_get_slices", "pd_get_slices_dev",
-    "pd_slice_norms", "pd_growth_rate",
+    "pd_slice_norms", "pd_growth_rate", "pd_profile_fine",
 ]
 
 
@@ -91,6 +91,7 @@ def _load():
         "pd_get_slices_dev": ([vp, vp, vp], i),
         "pd_slice_norms": ([vp, dp], i),
         "pd_growth_rate": ([vp, dp], i),
+        "pd_profile_fine": ([vp, i, dp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -232,6 +233,12 @@ class Context:
         out = np.empty(self.P + 1, np.float64)
         self._ok(lib.pd_slice_norms(self._h, _dptr(out)))
         return out
+
+    def profile_fine(self, reps: int = 20):
+        """(ms column kernel, ms row kernel, ms per fine step of a sweep)."""
+        ms = np.zeros(3, np.float64)
+        self._ok(lib.pd_profile_fine(self._h, int(reps), _dptr(ms)))
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def growth_rate(self) -> float:
         g = C.c_double()

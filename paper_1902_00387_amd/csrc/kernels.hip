@@ -450,6 +450,32 @@ hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields
 #undef CALL
 }
 
+hipError_t rows(int N, const FieldBatch& fb, const Problem& pb, int nfields, int mode, int last,
+                hipStream_t st) {
+  switch (N) {
+    case 16: return launch_rows<16>(fb, pb, nfields, mode, last, st);
+    case 32: return launch_rows<32>(fb, pb, nfields, mode, last, st);
+    case 64: return launch_rows<64>(fb, pb, nfields, mode, last, st);
+    case 128: return launch_rows<128>(fb, pb, nfields, mode, last, st);
+    case 256: return launch_rows<256>(fb, pb, nfields, mode, last, st);
+    case 512: return launch_rows<512>(fb, pb, nfields, mode, last, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int step,
+                hipStream_t st) {
+  switch (N) {
+    case 16: return launch_cols<16>(fb, pb, nfields, step, st);
+    case 32: return launch_cols<32>(fb, pb, nfields, step, st);
+    case 64: return launch_cols<64>(fb, pb, nfields, step, st);
+    case 128: return launch_cols<128>(fb, pb, nfields, step, st);
+    case 256: return launch_cols<256>(fb, pb, nfields, step, st);
+    case 512: return launch_cols<512>(fb, pb, nfields, step, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int NC>
 static hipError_t launch_sweep(const SweepArgs& a, const Problem& pb, hipStream_t st) {
   hipLaunchKernelGGL(k_sweep<NC>, dim3(1), dim3(512), 0, st, a, pb);

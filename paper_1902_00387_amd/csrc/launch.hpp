@@ -46,6 +46,11 @@ struct SweepArgs {
 
 hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                      int path, hipStream_t st);
+// single launches of the two phases of the multi-launch path
+hipError_t rows(int N, const FieldBatch& fb, const Problem& pb, int nfields, int mode, int last,
+                hipStream_t st);
+hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int step,
+                hipStream_t st);
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
 // full layout [f][3][N][N] <-> compact [f][3][M][M] of the |k| <= (M-1)/2 box
 // (M < box width of N restricts / zero-pads: Fourier re-sampling)

@@ -529,6 +529,62 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   return status;
 }
 
+pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (reps < 1 || !ms) return fail(c, PD_EINVAL, "reps must be >= 1 and ms non-null");
+  DeviceGuard dg(c->device);
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems();
+  const int P = c->P;
+  hipEvent_t ev[2];
+  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evf{ev};
+  auto fresh = [&]() -> hipError_t {
+    return hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx), hipMemcpyDeviceToDevice, st);
+  };
+  pd::FieldBatch fb;
+  fb.B = c->Fo.as<cplx>();
+  fb.H = c->Hf.as<cplx>();
+  fb.T1 = c->T1f.as<cplx>();
+  fb.T2 = c->T2f.as<cplx>();
+  fb.t0 = c->t0s.as<double>();
+  fb.tw = c->tw.as<cplx>();
+  const pd::Problem pf = make_problem(c, c->dtf);
+  float t = 0;
+  // a whole fine sweep (all slices, every step) as Parareal launches it
+  PD_HIP(c, fresh(), "copy");
+  PD_HIP(c, hipEventRecord(ev[0], st), "event");
+  PD_HIP(c, pd::propagate(c->N, fb, pf, P, c->nf, choose_path(c, P), st), "propagate");
+  PD_HIP(c, hipEventRecord(ev[1], st), "event");
+  PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+  PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+  ms[2] = t / c->nf;
+  ms[0] = ms[1] = 0.0;
+  if (choose_path(c, P) == pd::PATH_MULTI) {
+    // each phase kernel back to back, reps times, over the same batch
+    PD_HIP(c, fresh(), "copy");
+    PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    for (int i = 0; i < reps; ++i) PD_HIP(c, pd::cols(c->N, fb, pf, P, 1, st), "cols");
+    PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+    PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+    ms[0] = t / reps;
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    for (int i = 0; i < reps; ++i) PD_HIP(c, pd::rows(c->N, fb, pf, P, 2, 0, st), "rows");
+    PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+    PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+    ms[1] = t / reps;
+  }
+  return PD_OK;
+}
+
 pd_status pd_get_slices_dev(const pd_ctx* cc, void* d_out, void* s) {
   pd_ctx* c = const_cast<pd_ctx*>(cc);
   if (!c) return PD_EINVAL;
