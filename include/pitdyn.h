@@ -72,6 +72,15 @@ typedef enum {
   PD_PATH_SINGLE = 1   /* one workgroup per field runs every step         */
 } pd_path;
 
+typedef enum {
+  PD_COARSE_AUTO = 0,  /* convolution form when N_coarse <= 64, else FFT      */
+  PD_COARSE_FFT = 1,   /* same pseudo-spectral kernels as the fine propagator */
+  PD_COARSE_CONV = 2   /* explicit term as the exact spectral convolution with
+                          the flow's four Fourier modes (|k| = 1); equals the
+                          pseudo-spectral value to rounding since nothing
+                          aliases on the 2/3 box; N_coarse <= 64             */
+} pd_coarse_form;
+
 #define PD_MAX_ITER 256
 
 typedef struct {
@@ -108,6 +117,9 @@ pd_status pd_set_time(pd_ctx* ctx, double T, int n_slices, double dt_fine, doubl
 
 /* Choose how batched fine propagation is launched (testing and tuning). */
 pd_status pd_set_path(pd_ctx* ctx, pd_path path);
+/* Choose how pd_parareal's serial coarse sweep evaluates the explicit term
+   (one workgroup runs the whole sweep either way). */
+pd_status pd_set_coarse_form(pd_ctx* ctx, pd_coarse_form form);
 
 /* Initial field U_0, full layout [3][N][N], host or device memory. */
 pd_status pd_set_initial(pd_ctx* ctx, const double* b0);

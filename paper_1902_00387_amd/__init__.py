@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(HERE, "libpitdyn.so")
 FLOW_NONE, FLOW_ROBERTS, FLOW_GP = 0, 1, 2
 FLOWS = {"none": FLOW_NONE, "roberts": FLOW_ROBERTS, "gp": FLOW_GP}
 PATH_AUTO, PATH_MULTI, PATH_SINGLE = -1, 0, 1
+COARSE_AUTO, COARSE_FFT, COARSE_CONV = 0, 1, 2
 MAX_ITER = 256
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, EUNSTABLE = 0, 1, -1, -2, -3, -4, -5
@@ -33,7 +34,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, EUNSTABLE = 0, 1, -1, -2, -3, -
 # every symbol include/pitdyn.h declares
 SYMBOLS = [
     "pd_create", "pd_destroy", "pd_last_error", "pd_set_stream", "pd_set_problem",
-    "pd_set_time", "pd_set_path", "pd_set_initial", "pd_set_initial_dev", "pd_fine_dev",
+    "pd_set_time", "pd_set_path", "pd_set_coarse_form", "pd_set_initial", "pd_set_initial_dev", "pd_fine_dev",
     "pd_coarse_dev", "pd_steps_dev", "pd_parareal", "pd_get_slices", "pd_get_slices_dev",
     "pd_slice_norms", "pd_growth_rate", "pd_profile_fine",
 ]
@@ -81,6 +82,7 @@ def _load():
         "pd_set_problem": ([vp, i, d, d, i], i),
         "pd_set_time": ([vp, d, i, d, d, i], i),
         "pd_set_path": ([vp, i], i),
+        "pd_set_coarse_form": ([vp, i], i),
         "pd_set_initial": ([vp, dp], i),
         "pd_set_initial_dev": ([vp, vp, vp], i),
         "pd_fine_dev": ([vp, dp, i, vp, vp, vp], i),
@@ -169,6 +171,9 @@ class Context:
 
     def set_path(self, path: int):
         self._ok(lib.pd_set_path(self._h, int(path)))
+
+    def set_coarse_form(self, form: int):
+        self._ok(lib.pd_set_coarse_form(self._h, int(form)))
 
     def set_stream(self, stream_handle):
         self._ok(lib.pd_set_stream(self._h, C.c_void_p(stream_handle)))

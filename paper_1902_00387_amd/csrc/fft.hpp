@@ -1,15 +1,13 @@
 // Register/LDS complex FFT building blocks for gfx950 (FP64).
 //
-// A group of T = N/8 lanes transforms one length-N sequence.  Lane j holds
-// eight values in registers, v[e] = x[j + T*e] ("strided layout").  Each
+// A group of T = N/E lanes (E = 8 or 4) of one wavefront transforms one
+// length-N sequence.  Lane j holds E values in registers, v[e] = x[j + T*e]
+// ("strided layout").  Each
 // pass is a mixed-radix Stockham step: butterfly b gathers x[b + k*N/R]
 // (k < R), which for the strided layout are the lane's own registers, so a
 // pass needs no load exchange; its outputs go to LDS at their autosorted
 // positions and are read back in the strided layout for the next pass.  The
 // final read-back leaves the transform in natural order, again strided.
-//
-// Plans (radices, all passes with eight values per lane):
-//   16: 8x2   32: 8x4   64: 8x8   128: 8x8x2   256: 8x8x4   512: 8x8x8
 //
 // DIR = -1 is the forward transform X_k = sum_n x_n e^{-2 pi i nk/N},
 // DIR = +1 the unnormalised inverse.  Twiddles come from a table
@@ -97,12 +95,23 @@ __device__ __forceinline__ void dftR(cplx* x) {
   else dft8<DIR>(x);
 }
 
-// One Stockham pass of radix R over sub-transforms of length NS.
-// Lane j owns butterflies b = j + T*q, q < 8/R.  Outputs are scattered to
-// LDS (padded), then the lane reads back its strided values.
-template <int N, int R, int NS, int DIR>
+// Orders the LDS exchange of one transform.  Every transform group lies
+// inside one wavefront, whose lanes issue each LDS instruction together and
+// whose LDS operations complete in order, so the exchange only has to stop the
+// compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One Stockham pass of radix R over sub-transforms of length NS, E values a
+// lane.  Lane j owns butterflies b = j + T*q, q < E/R (T = N/E lanes).
+// Outputs are scattered to LDS (padded), then the lane reads back its
+// strided values.
+template <int N, int E, int R, int NS, int DIR>
 __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* __restrict__ tw) {
-  constexpr int T = N / 8, Q = 8 / R;
+  constexpr int T = N / E, Q = E / R;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int b = j + T * q;
@@ -122,39 +131,40 @@ __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* __
 #pragma unroll
     for (int k = 0; k < R; ++k) s[lpad(base + k * NS)] = x[k];
   }
-  __syncthreads();
+  group_sync();
 #pragma unroll
-  for (int e = 0; e < 8; ++e) v[e] = s[lpad(j + T * e)];
-  __syncthreads();
+  for (int e = 0; e < E; ++e) v[e] = s[lpad(j + T * e)];
+  group_sync();
 }
 
-// Full length-N transform of the strided register vector v (see header).
-// s: this group's LDS span (LdsSpan<N>::value entries).  All lanes of the
-// workgroup must call it (it contains workgroup barriers).
-template <int N, int DIR>
+// Full length-N transform of the strided register vector v (E values a
+// lane, T = N/E lanes, all in one wavefront; see header).  s: this group's
+// LDS span (LdsSpan<N>::value entries).
+//   E = 8: 16: 8x2   32: 8x4   64: 8x8   128: 8x8x2   256: 8x8x4   512: 8x8x8
+//   E = 4: 16: 4x4   32: 4x4x2   64: 4x4x4   128: 4x4x4x2   256: 4x4x4x4
+template <int N, int E, int DIR>
 __device__ __forceinline__ void fft(cplx* v, cplx* s, int j, const cplx* __restrict__ tw) {
   static_assert(N >= 16 && N <= 512 && (N & (N - 1)) == 0, "N");
-  if constexpr (N == 16) {
-    fft_pass<N, 8, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 2, 8, DIR>(v, s, j, tw);
-  } else if constexpr (N == 32) {
-    fft_pass<N, 8, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 4, 8, DIR>(v, s, j, tw);
-  } else if constexpr (N == 64) {
-    fft_pass<N, 8, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 8, 8, DIR>(v, s, j, tw);
-  } else if constexpr (N == 128) {
-    fft_pass<N, 8, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 8, 8, DIR>(v, s, j, tw);
-    fft_pass<N, 2, 64, DIR>(v, s, j, tw);
-  } else if constexpr (N == 256) {
-    fft_pass<N, 8, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 8, 8, DIR>(v, s, j, tw);
-    fft_pass<N, 4, 64, DIR>(v, s, j, tw);
+  static_assert((E == 8 && N / E <= 64) || (E == 4 && N / E <= 64), "group must fit a wavefront");
+  if constexpr (E == 8) {
+    fft_pass<N, 8, 8, 1, DIR>(v, s, j, tw);
+    if constexpr (N == 16) fft_pass<N, 8, 2, 8, DIR>(v, s, j, tw);
+    else if constexpr (N == 32) fft_pass<N, 8, 4, 8, DIR>(v, s, j, tw);
+    else {
+      fft_pass<N, 8, 8, 8, DIR>(v, s, j, tw);
+      if constexpr (N == 128) fft_pass<N, 8, 2, 64, DIR>(v, s, j, tw);
+      else if constexpr (N == 256) fft_pass<N, 8, 4, 64, DIR>(v, s, j, tw);
+      else if constexpr (N == 512) fft_pass<N, 8, 8, 64, DIR>(v, s, j, tw);
+    }
   } else {
-    fft_pass<N, 8, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 8, 8, DIR>(v, s, j, tw);
-    fft_pass<N, 8, 64, DIR>(v, s, j, tw);
+    fft_pass<N, 4, 4, 1, DIR>(v, s, j, tw);
+    fft_pass<N, 4, 4, 4, DIR>(v, s, j, tw);
+    if constexpr (N == 32) fft_pass<N, 4, 2, 16, DIR>(v, s, j, tw);
+    else if constexpr (N >= 64) {
+      fft_pass<N, 4, 4, 16, DIR>(v, s, j, tw);
+      if constexpr (N == 128) fft_pass<N, 4, 2, 64, DIR>(v, s, j, tw);
+      else if constexpr (N == 256) fft_pass<N, 4, 4, 64, DIR>(v, s, j, tw);
+    }
   }
 }
 

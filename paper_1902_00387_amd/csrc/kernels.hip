@@ -23,17 +23,24 @@
 
 namespace pd {
 
-template <int N>
+template <int N, int E>
 struct Geo {
   static constexpr int K = (N - 1) / 3;
   static constexpr int M = 2 * K + 1;
-  static constexpr int T = N / 8;           // lanes per transform
+  static constexpr int T = N / E;           // lanes per transform (one wavefront at most)
   static constexpr int SPAN = LdsSpan<N>::value;
-  // multi-launch shapes: rows per workgroup, columns per workgroup
-  static constexpr int RPW = (64 / T) > 0 ? 64 / T : 1;
-  static constexpr int TX = N <= 32 ? 16 : (N <= 128 ? 8 : 4);
-  // single-workgroup (persistent) shape: FFT groups per 512-lane workgroup
-  static constexpr int NG = 512 / T;
+};
+
+// Transform shapes of the launches (values a lane E; rows per 64-lane row
+// workgroup; columns per column workgroup; lanes of the single-workgroup path).
+template <int N>
+struct Shape {
+  static constexpr int ER = N == 512 ? 8 : 8;    // row phase, multi-launch path
+  static constexpr int EC = N == 512 ? 8 : 4;    // column phase, multi-launch path
+  static constexpr int TXC = N <= 64 ? 32 : (N <= 256 ? 16 : 8);  // columns per column workgroup
+  static constexpr int ESR = 8;                  // single-workgroup path, rows
+  static constexpr int ESC = N == 512 ? 8 : 4;   // single-workgroup path, columns
+  static constexpr int LANES = 512;
 };
 
 __device__ __forceinline__ int signed_k(int m, int N) { return m < N / 2 ? m : m - N; }
@@ -64,23 +71,24 @@ __device__ __forceinline__ FlowPhase flow_phase(const Problem& pb, double t) {
 }
 
 // ---------------------------------------------------------------------------
-// Row phase of one box row r of one field, by one group of T lanes (lane j).
+// Row phase of one box row r of one field, by one group of T lanes (lane j)
+// inside a wavefront; no workgroup barrier.
 // mode 0: start of a slice (inverse transform of the state only);
 // mode 1: SBDF1 update; mode 2: SBDF2 update.  last: skip the inverse.
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cplx* __restrict__ B,
                                           cplx* __restrict__ H, const cplx* __restrict__ T2,
                                           cplx* __restrict__ T1, const cplx* __restrict__ tw,
                                           const Problem& pb, int mode, bool last) {
-  using G = Geo<N>;
+  using G = Geo<N, E>;
   constexpr int T = G::T, K = G::K, M = G::M;
-  cplx w[3][8];
+  cplx w[3][E];
   const int ky = r - K;
   if (mode == 0) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < E; ++e) {
         const int kx = signed_k(j + T * e, N);
         w[c][e] = (active && kx >= -K && kx <= K) ? B[(c * M + r) * M + kx + K] : czero();
       }
@@ -88,13 +96,13 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : czero();
-      fft<N, -1>(w[c], s, j, tw);
+      for (int e = 0; e < E; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : czero();
+      fft<N, E, -1>(w[c], s, j, tw);
     }
     const double sc = 1.0 / ((double)N * (double)N);
     const double dt = pb.dt, kz = pb.kz;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
       const int kx = signed_k(j + T * e, N);
       if (active && kx >= -K && kx <= K) {
         const cplx ex = cscale(w[0][e], sc), ey = cscale(w[1][e], sc), ez = cscale(w[2][e], sc);
@@ -131,31 +139,48 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
   if (!last) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      fft<N, 1>(w[c], s, j, tw);
+      fft<N, E, 1>(w[c], s, j, tw);
       if (active) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) T1[(c * M + r) * N + j + T * e] = w[c][e];
+        for (int e = 0; e < E; ++e) T1[(c * M + r) * N + j + T * e] = w[c][e];
       }
     }
   }
 }
 
-// Column phase of one grid column x of one field at time t.
-template <int N>
-__device__ __forceinline__ void col_phase(int x, bool active, int j, cplx* s,
-                                          const cplx* __restrict__ T1, cplx* __restrict__ T2,
-                                          const cplx* __restrict__ tw, const FlowPhase& fp) {
-  using G = Geo<N>;
+// Column phase of the columns [x0, x0 + TX) of one field at time t, by the
+// whole workgroup (TX = blockDim / T groups; group g owns column x0 + g).
+// Rows are staged through an LDS tile (pitch TX + 1) so that global loads
+// and stores run along x, TX values at a time; each group transforms its
+// column in registers with its own LDS span for the exchanges.
+template <int N, int E>
+__device__ __forceinline__ void col_tile(int x0, cplx* tile, cplx* spans,
+                                         const cplx* __restrict__ T1, cplx* __restrict__ T2,
+                                         const cplx* __restrict__ tw, const FlowPhase& fp) {
+  using G = Geo<N, E>;
   constexpr int T = G::T, K = G::K, M = G::M;
-  cplx w[3][8];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int TX = nthr / T < N ? nthr / T : N;
+  const int TP = TX + 1;
+  const int g = tid / T, j = tid % T;
+  const int x = x0 + g;
+  const bool active = g < TX && x < N;
+  cplx* s = spans + (g < TX ? g : 0) * G::SPAN;
+  cplx w[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int ky = signed_k(j + T * e, N);
-      w[c][e] = (active && ky >= -K && ky <= K) ? T1[(c * M + ky + K) * N + x] : czero();
+    for (int i = tid; i < M * TX; i += nthr) {
+      const int r = i / TX, cc = i - r * TX;
+      tile[r * TP + cc] = (x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : czero();
     }
-    fft<N, 1>(w[c], s, j, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int ky = signed_k(j + T * e, N);
+      w[c][e] = (active && ky >= -K && ky <= K) ? tile[(ky + K) * TP + g] : czero();
+    }
+    if (g < TX) fft<N, E, 1>(w[c], s, j, tw);
+    __syncthreads();
   }
   // E = u x b at (x, y_e)
   const int xa = active ? x : 0;
@@ -163,7 +188,7 @@ __device__ __forceinline__ void col_phase(int x, bool active, int j, cplx* s,
   const double cxp = cx * fp.cpx - sx * fp.spx;   // cos(x + px)
   const double sxp = sx * fp.cpx + cx * fp.spx;   // sin(x + px)
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int m = j + T * e;
     const double cy = tw[m].re, sy = -tw[m].im;
     const double cyp = cy * fp.cpy - sy * fp.spy;  // cos(y + py)
@@ -176,80 +201,107 @@ __device__ __forceinline__ void col_phase(int x, bool active, int j, cplx* s,
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    fft<N, -1>(w[c], s, j, tw);
-    if (active) {
+    if (g < TX) {
+      fft<N, E, -1>(w[c], s, j, tw);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < E; ++e) {
         const int ky = signed_k(j + T * e, N);
-        if (ky >= -K && ky <= K) T2[(c * M + ky + K) * N + x] = w[c][e];
+        if (ky >= -K && ky <= K) tile[(ky + K) * TP + g] = w[c][e];
       }
     }
+    __syncthreads();
+    for (int i = tid; i < M * TX; i += nthr) {
+      const int r = i / TX, cc = i - r * TX;
+      if (x0 + cc < N) T2[(c * M + r) * N + x0 + cc] = tile[r * TP + cc];
+    }
+    __syncthreads();
   }
+}
+
+template <int N, int E>
+__host__ __device__ constexpr int tile_elems(int lanes) {
+  return Geo<N, E>::M * ((lanes / Geo<N, E>::T < N ? lanes / Geo<N, E>::T : N) + 1);
 }
 
 // ---------------------------------------------------------------------------
 // Multi-launch path: one launch per phase over every (field, tile).
 template <int N>
 __global__ __launch_bounds__(64) void k_rows(FieldBatch fb, Problem pb, int mode, int last) {
-  using G = Geo<N>;
-  __shared__ cplx sm[G::RPW * G::SPAN];
+  constexpr int E = Shape<N>::ER;
+  using G = Geo<N, E>;
+  constexpr int RPW = 64 / G::T;
+  __shared__ cplx sm[RPW * G::SPAN];
   const int g = threadIdx.x / G::T, j = threadIdx.x % G::T;
-  const int r = blockIdx.x * G::RPW + g;
+  const int r = blockIdx.x * RPW + g;
   const size_t f = blockIdx.y;
   const size_t box = (size_t)3 * G::M * G::M, rows = (size_t)3 * G::M * N;
-  row_phase<N>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
-               fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, pb, mode, last != 0);
+  row_phase<N, E>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
+                  fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, pb, mode, last != 0);
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void k_cols(FieldBatch fb, Problem pb, int step) {
-  using G = Geo<N>;
-  __shared__ cplx sm[G::TX * G::SPAN];
-  const int tx = threadIdx.x % G::TX, j = threadIdx.x / G::TX;
-  const int x = blockIdx.x * G::TX + tx;
+__global__ __launch_bounds__(Shape<N>::TXC * (N / Shape<N>::EC)) void k_cols(FieldBatch fb,
+                                                                           Problem pb, int step) {
+  constexpr int E = Shape<N>::EC, TX = Shape<N>::TXC;
+  using G = Geo<N, E>;
+  __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
+  __shared__ cplx spans[TX * G::SPAN];
   const size_t f = blockIdx.y;
   const size_t rows = (size_t)3 * G::M * N;
   const FlowPhase fp = flow_phase(pb, fb.t0[f] + step * pb.dt);
-  col_phase<N>(x, x < N, j, sm + tx * G::SPAN, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
+  col_tile<N, E>(blockIdx.x * TX, tile, spans, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
 }
 
 // ---------------------------------------------------------------------------
-// Single-workgroup path: one 512-lane workgroup owns a field and runs every
-// step of the slice; the two phases meet at workgroup barriers, the row
-// buffers stay in this workgroup's slice of global memory.
+// Single-workgroup path: one workgroup owns a field and runs every step of
+// the slice; the two phases meet at workgroup barriers, the row buffers stay
+// in this workgroup's slice of global memory.
 template <int N>
-__device__ __forceinline__ void propagate_wg(cplx* sm, cplx* B, cplx* H, cplx* T1, cplx* T2,
-                                             const cplx* tw, const Problem& pb, double t0,
-                                             int nsteps) {
-  using G = Geo<N>;
-  constexpr int T = G::T, NG = G::NG, M = G::M;
+struct SingleLds {
+  static constexpr int L = Shape<N>::LANES;
+  using GR = Geo<N, Shape<N>::ESR>;
+  using GC = Geo<N, Shape<N>::ESC>;
+  using G = GR;
+  static constexpr int NGR = L / GR::T, NGC = L / GC::T;
+  static constexpr int TILE = tile_elems<N, Shape<N>::ESC>(L);
+  static constexpr int SPANS = (NGR > NGC ? NGR : NGC) * GR::SPAN;
+};
+
+template <int N>
+__device__ __forceinline__ void propagate_wg(cplx* tile, cplx* spans, cplx* B, cplx* H, cplx* T1,
+                                             cplx* T2, const cplx* tw, const Problem& pb,
+                                             double t0, int nsteps) {
+  using S = SingleLds<N>;
+  constexpr int ER = Shape<N>::ESR, EC = Shape<N>::ESC;
+  constexpr int TR = S::GR::T, M = S::GR::M, NGR = S::NGR, NGC = S::NGC;
+  constexpr int TX = NGC < N ? NGC : N;
   const int tid = threadIdx.x;
-  const int rg = tid / T, rj = tid % T;   // row phase: lanes of a group adjacent
-  const int cg = tid % NG, cj = tid / NG; // column phase: groups adjacent (coalesced x)
-  for (int r0 = 0; r0 < M; r0 += NG)
-    row_phase<N>(r0 + rg, r0 + rg < M, rj, sm + rg * G::SPAN, B, H, T2, T1, tw, pb, 0, false);
+  const int rg = tid / TR, rj = tid % TR;
+  for (int r0 = 0; r0 < M; r0 += NGR)
+    row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb, 0,
+                     false);
   __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
     const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
-    for (int x0 = 0; x0 < N; x0 += NG)
-      col_phase<N>(x0 + cg, x0 + cg < N, cj, sm + cg * G::SPAN, T1, T2, tw, fp);
-    __syncthreads();
+    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC>(x0, tile, spans, T1, T2, tw, fp);
     const int mode = step == 0 ? 1 : 2;
     const bool last = step == nsteps - 1;
-    for (int r0 = 0; r0 < M; r0 += NG)
-      row_phase<N>(r0 + rg, r0 + rg < M, rj, sm + rg * G::SPAN, B, H, T2, T1, tw, pb, mode, last);
+    for (int r0 = 0; r0 < M; r0 += NGR)
+      row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb,
+                       mode, last);
     __syncthreads();
   }
 }
 
 template <int N>
-__global__ __launch_bounds__(512) void k_slice(FieldBatch fb, Problem pb, int nsteps) {
-  using G = Geo<N>;
-  __shared__ cplx sm[G::NG * G::SPAN];
+__global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Problem pb, int nsteps) {
+  using S = SingleLds<N>;
+  __shared__ cplx tile[S::TILE];
+  __shared__ cplx spans[S::SPANS];
   const size_t f = blockIdx.x;
-  const size_t box = (size_t)3 * G::M * G::M, rows = (size_t)3 * G::M * N;
-  propagate_wg<N>(sm, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw,
-                  pb, fb.t0[f], nsteps);
+  const size_t box = (size_t)3 * S::GR::M * S::GR::M, rows = (size_t)3 * S::GR::M * N;
+  propagate_wg<N>(tile, spans, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows,
+                  fb.tw, pb, fb.t0[f], nsteps);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,11 +315,12 @@ __global__ __launch_bounds__(512) void k_slice(FieldBatch fb, Problem pb, int ns
 // maps.  After the last slice the defect sums |U_P - Uprev_P|^2 and |U_P|^2
 // are reduced in a fixed order into red[0], red[1].
 template <int NC>
-__global__ __launch_bounds__(512) void k_sweep(SweepArgs a, Problem pb) {
-  using G = Geo<NC>;
-  __shared__ cplx sm[G::NG * G::SPAN];
-  __shared__ double rs[2][512];
-  constexpr int Mc = G::M, Kc = G::K;
+__global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem pb) {
+  using S = SingleLds<NC>;
+  __shared__ cplx tile[S::TILE];
+  __shared__ cplx spans[S::SPANS];
+  __shared__ double rs[2][Shape<NC>::LANES];
+  constexpr int Mc = S::GR::M, Kc = S::GR::K;
   const int M = a.M, K = (a.M - 1) / 2;
   const size_t fbox = (size_t)3 * M * M;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -278,7 +331,7 @@ __global__ __launch_bounds__(512) void k_sweep(SweepArgs a, Problem pb) {
       a.Bc[i] = Un[(c * M + rr + K - Kc) * M + cc + K - Kc];
     }
     __syncthreads();
-    propagate_wg<NC>(sm, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, n * a.dT, a.nsteps);
+    propagate_wg<NC>(tile, spans, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, n * a.dT, a.nsteps);
     cplx* Un1 = a.U + (n + 1) * fbox;
     cplx* Go = a.Gold + n * fbox;
     const cplx* Fn = a.Fo + n * fbox;
@@ -287,6 +340,194 @@ __global__ __launch_bounds__(512) void k_sweep(SweepArgs a, Problem pb) {
       const int dr = r - K, dc = cc - K;
       cplx g = czero();
       if (dr >= -Kc && dr <= Kc && dc >= -Kc && dc <= Kc) g = a.Bc[(c * Mc + dr + Kc) * Mc + dc + Kc];
+      if (a.mode == 0) {
+        Un1[i] = g;
+      } else {
+        Un1[i] = cadd(Fn[i], csub(g, Go[i]));
+      }
+      Go[i] = g;
+    }
+    __syncthreads();
+  }
+  if (a.mode != 0 && a.red != nullptr) {
+    const cplx* UP = a.U + (size_t)a.P * fbox;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = tid; i < (int)fbox; i += nt) {
+      const cplx d = csub(UP[i], a.Uprev[i]);
+      s0 += d.re * d.re + d.im * d.im;
+      s1 += UP[i].re * UP[i].re + UP[i].im * UP[i].im;
+    }
+    rs[0][tid] = s0;
+    rs[1][tid] = s1;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        rs[0][tid] += rs[0][tid + w];
+        rs[1][tid] += rs[1][tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      a.red[0] = rs[0][0];
+      a.red[1] = rs[1][0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse sweep, spectral-convolution form.  Each flow of Section 2 has only
+// four Fourier modes, q = (+-1, 0) and (0, +-1) (ky, kx), so the explicit term
+// on the 2/3 box is the exact convolution E_k = sum_q u_q x b_{k-q}: products
+// of box modes reach |k| <= K + 1 < N/2 and nothing aliases, hence this
+// equals the pseudo-spectral evaluation (transform, multiply, transform,
+// truncate) up to rounding.  On the serial coarse path this replaces the two
+// transposes of a step by one pass over the box held in LDS.
+//
+// Flow coefficients (u written as sums of e^{i q.x}, px = cos t, py = sin t
+// for Galloway-Proctor, 0 for Roberts):
+//   q = (+1, 0): u_q = (A/2) e^{+i py} (1, 0, -i)
+//   q = (-1, 0): u_q = (A/2) e^{-i py} (1, 0, +i)
+//   q = (0, +1): u_q = (A/2) e^{+i px} (0, -i, 1)
+//   q = (0, -1): u_q = (A/2) e^{-i px} (0, +i, 1)
+// The four coefficients alpha_+- = (A/2) e^{+-i py}, beta_+- = (A/2) e^{+-i px}.
+struct FlowModes {
+  cplx ap, am, bp, bm;
+};
+
+__device__ __forceinline__ FlowModes flow_modes(const Problem& pb, double t) {
+  double px = 0.0, py = 0.0;
+  if (pb.tdep) {
+    px = cos(t);
+    py = sin(t);
+  }
+  double spx, cpx, spy, cpy;
+  sincos(px, &spx, &cpx);
+  sincos(py, &spy, &cpy);
+  const double h = 0.5 * pb.amp;
+  FlowModes f;
+  f.ap = {h * cpy, h * spy};
+  f.am = {h * cpy, -h * spy};
+  f.bp = {h * cpx, h * spx};
+  f.bm = {h * cpx, -h * spx};
+  return f;
+}
+
+constexpr int CONV_LANES = 1024;
+constexpr int CONV_MMAX = 45;  // coarse box width held in LDS (N_C <= 64)
+constexpr int CONV_MPL = (CONV_MMAX * CONV_MMAX + CONV_LANES - 1) / CONV_LANES;  // modes a lane
+
+// One workgroup runs the coarse sweep; lane l owns box modes l + CONV_LANES*m
+// (state and history in registers) and reads neighbours from LDS.
+__global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem pb, int Mc) {
+  __shared__ cplx bs[3 * CONV_MMAX * CONV_MMAX];
+  __shared__ double rs[2][CONV_LANES];
+  const int Kc = (Mc - 1) / 2;
+  const int nbox = Mc * Mc;
+  const int M = a.M, K = (a.M - 1) / 2;
+  const size_t fbox = (size_t)3 * M * M;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double kz = pb.kz, dt = pb.dt;
+  // owned modes
+  int own[CONV_MPL], oky[CONV_MPL], okx[CONV_MPL];
+#pragma unroll
+  for (int m = 0; m < CONV_MPL; ++m) {
+    own[m] = tid + m * nt;
+    const int i = own[m] < nbox ? own[m] : 0;
+    oky[m] = i / Mc - Kc;
+    okx[m] = i % Mc - Kc;
+  }
+  for (int n = a.n0; n < a.P; ++n) {
+    const cplx* Un = a.U + n * fbox;
+    cplx h[CONV_MPL][3];
+#pragma unroll
+    for (int m = 0; m < CONV_MPL; ++m)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        h[m][c] = czero();
+        if (own[m] < nbox) bs[c * nbox + own[m]] = Un[(c * M + oky[m] + K) * M + okx[m] + K];
+      }
+    __syncthreads();
+    const double t0 = n * a.dT;
+    for (int step = 0; step < a.nsteps; ++step) {
+      const FlowModes fm = flow_modes(pb, t0 + step * dt);
+      cplx bn[CONV_MPL][3];
+#pragma unroll
+      for (int m = 0; m < CONV_MPL; ++m) {
+        if (own[m] >= nbox) continue;
+        // u_q x b_{k-q}, written out for the four u_q above:
+        //  q = (+1,0), u = ap (1, 0, -i): ( i ap by, -i ap bx - ap bz,  ap by)
+        //  q = (-1,0), u = am (1, 0, +i): (-i am by,  i am bx - am bz,  am by)
+        //  q = (0,+1), u = bp (0, -i, 1): (-i bp bz - bp by,  bp bx,  i bp bx)
+        //  q = (0,-1), u = bm (0, +i, 1): ( i bm bz - bm by,  bm bx, -i bm bx)
+        cplx e[3] = {czero(), czero(), czero()};
+        const int ky = oky[m], kx = okx[m];
+        if (ky - 1 >= -Kc) {
+          const int si = (ky - 1 + Kc) * Mc + kx + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx aby = cmul(fm.ap, by);
+          e[0] = cadd(e[0], mul_i<1>(aby));
+          e[1] = csub(e[1], cadd(mul_i<1>(cmul(fm.ap, bx)), cmul(fm.ap, bz)));
+          e[2] = cadd(e[2], aby);
+        }
+        if (ky + 1 <= Kc) {
+          const int si = (ky + 1 + Kc) * Mc + kx + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx aby = cmul(fm.am, by);
+          e[0] = csub(e[0], mul_i<1>(aby));
+          e[1] = cadd(e[1], csub(mul_i<1>(cmul(fm.am, bx)), cmul(fm.am, bz)));
+          e[2] = cadd(e[2], aby);
+        }
+        if (kx - 1 >= -Kc) {
+          const int si = (ky + Kc) * Mc + kx - 1 + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx bbx = cmul(fm.bp, bx);
+          e[0] = csub(e[0], cadd(mul_i<1>(cmul(fm.bp, bz)), cmul(fm.bp, by)));
+          e[1] = cadd(e[1], bbx);
+          e[2] = cadd(e[2], mul_i<1>(bbx));
+        }
+        if (kx + 1 <= Kc) {
+          const int si = (ky + Kc) * Mc + kx + 1 + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx bbx = cmul(fm.bm, bx);
+          e[0] = cadd(e[0], csub(mul_i<1>(cmul(fm.bm, bz)), cmul(fm.bm, by)));
+          e[1] = cadd(e[1], bbx);
+          e[2] = csub(e[2], mul_i<1>(bbx));
+        }
+        const double kxd = kx, kyd = ky;
+        const double aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / pb.Rm;
+        cplx nl[3];
+        nl[0] = mul_i<1>(csub(cscale(e[2], kyd), cscale(e[1], kz)));
+        nl[1] = mul_i<1>(csub(cscale(e[0], kz), cscale(e[2], kxd)));
+        nl[2] = mul_i<1>(csub(cscale(e[1], kxd), cscale(e[0], kyd)));
+        const double inv = step == 0 ? 1.0 / (1.0 + aa) : 1.0 / (1.5 + aa);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const cplx b = bs[c * nbox + own[m]];
+          if (step == 0) {
+            bn[m][c] = cscale(cadd(b, cscale(nl[c], dt)), inv);
+          } else {
+            bn[m][c] = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), h[m][c]), inv);
+          }
+          h[m][c] = csub(cscale(b, -0.5), cscale(nl[c], dt));
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < CONV_MPL; ++m)
+        if (own[m] < nbox)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) bs[c * nbox + own[m]] = bn[m][c];
+      __syncthreads();
+    }
+    // correction on the fine box: g = zero-padded coarse result
+    cplx* Un1 = a.U + (n + 1) * fbox;
+    cplx* Go = a.Gold + n * fbox;
+    const cplx* Fn = a.Fo + n * fbox;
+    for (int i = tid; i < (int)fbox; i += nt) {
+      const int c = i / (M * M), r = (i / M) % M, cc = i % M;
+      const int dr = r - K, dc = cc - K;
+      cplx g = czero();
+      if (dr >= -Kc && dr <= Kc && dc >= -Kc && dc <= Kc) g = bs[c * nbox + (dr + Kc) * Mc + dc + Kc];
       if (a.mode == 0) {
         Un1[i] = g;
       } else {
@@ -388,25 +629,26 @@ __global__ __launch_bounds__(256) void k_norm2(const cplx* __restrict__ x, size_
 template <int N>
 static hipError_t launch_rows(const FieldBatch& fb, const Problem& pb, int nfields, int mode,
                               int last, hipStream_t st) {
-  using G = Geo<N>;
-  dim3 grid((G::M + G::RPW - 1) / G::RPW, nfields);
-  hipLaunchKernelGGL(k_rows<N>, grid, dim3(G::RPW * G::T), 0, st, fb, pb, mode, last);
+  using G = Geo<N, Shape<N>::ER>;
+  constexpr int RPW = 64 / G::T;
+  dim3 grid((G::M + RPW - 1) / RPW, nfields);
+  hipLaunchKernelGGL(k_rows<N>, grid, dim3(64), 0, st, fb, pb, mode, last);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_cols(const FieldBatch& fb, const Problem& pb, int nfields, int step,
                               hipStream_t st) {
-  using G = Geo<N>;
-  dim3 grid(N / G::TX, nfields);
-  hipLaunchKernelGGL(k_cols<N>, grid, dim3(G::TX * G::T), 0, st, fb, pb, step);
+  constexpr int TX = Shape<N>::TXC, T = N / Shape<N>::EC;
+  dim3 grid((N + TX - 1) / TX, nfields);
+  hipLaunchKernelGGL(k_cols<N>, grid, dim3(TX * T), 0, st, fb, pb, step);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_slice(const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_slice<N>, dim3(nfields), dim3(512), 0, st, fb, pb, nsteps);
+  hipLaunchKernelGGL(k_slice<N>, dim3(nfields), dim3(Shape<N>::LANES), 0, st, fb, pb, nsteps);
   return hipGetLastError();
 }
 
@@ -478,7 +720,14 @@ hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int
 
 template <int NC>
 static hipError_t launch_sweep(const SweepArgs& a, const Problem& pb, hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep<NC>, dim3(1), dim3(512), 0, st, a, pb);
+  hipLaunchKernelGGL(k_sweep<NC>, dim3(1), dim3(Shape<NC>::LANES), 0, st, a, pb);
+  return hipGetLastError();
+}
+
+hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
+  const int Mc = 2 * ((Nc - 1) / 3) + 1;
+  if (Mc > CONV_MMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sweep_conv, dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc);
   return hipGetLastError();
 }
 

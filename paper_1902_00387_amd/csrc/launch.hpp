@@ -52,6 +52,9 @@ hipError_t rows(int N, const FieldBatch& fb, const Problem& pb, int nfields, int
 hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int step,
                 hipStream_t st);
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
+// same sweep with the explicit term as the exact spectral convolution with the
+// flow's four Fourier modes (N_C <= 64)
+hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
 // full layout [f][3][N][N] <-> compact [f][3][M][M] of the |k| <= (M-1)/2 box
 // (M < box width of N restricts / zero-pads: Fourier re-sampling)
 hipError_t pack(const cplx* full, cplx* box, int N, int M, size_t nfields, hipStream_t st);

@@ -103,6 +103,7 @@ struct pd_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int path = PD_PATH_AUTO;
+  int coarse_form = PD_COARSE_AUTO;
   // problem
   bool have_problem = false;
   int flow = PD_FLOW_NONE;
@@ -169,6 +170,11 @@ pd::Problem make_problem(const pd_ctx* c, double dt) {
   pb.amp = c->flow == PD_FLOW_NONE ? 0.0 : (c->flow == PD_FLOW_ROBERTS ? 1.0 : std::sqrt(1.5));
   pb.tdep = c->flow == PD_FLOW_GP ? 1 : 0;
   return pb;
+}
+
+bool use_conv_sweep(const pd_ctx* c) {
+  if (c->coarse_form == PD_COARSE_FFT) return false;
+  return c->Nc <= 64;
 }
 
 int choose_path(const pd_ctx* c, int nfields) {
@@ -294,6 +300,16 @@ pd_status pd_set_path(pd_ctx* c, pd_path p) {
   if (p != PD_PATH_AUTO && p != PD_PATH_MULTI && p != PD_PATH_SINGLE)
     return fail(c, PD_EINVAL, "unknown path %d", (int)p);
   c->path = p;
+  return PD_OK;
+}
+
+pd_status pd_set_coarse_form(pd_ctx* c, pd_coarse_form f) {
+  if (!c) return PD_EINVAL;
+  if (f != PD_COARSE_AUTO && f != PD_COARSE_FFT && f != PD_COARSE_CONV)
+    return fail(c, PD_EINVAL, "unknown coarse form %d", (int)f);
+  if (f == PD_COARSE_CONV && c->have_time && c->Nc > 64)
+    return fail(c, PD_EINVAL, "the convolution coarse sweep needs N_coarse <= 64");
+  c->coarse_form = f;
   return PD_OK;
 }
 
@@ -471,7 +487,10 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   sa.n0 = 0;
   sa.mode = 0;
   PD_HIP(c, hipEventRecord(ev[0], st), "event");
-  PD_HIP(c, pd::sweep(c->Nc, sa, pc, st), "coarse sweep");
+  auto run_sweep = [&]() -> hipError_t {
+    return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
+  };
+  PD_HIP(c, run_sweep(), "coarse sweep");
   PD_HIP(c, hipEventRecord(ev[1], st), "event");
   PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
   float ms = 0;
@@ -500,7 +519,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     // serial coarse sweep with the correction, then the defect sums
     sa.n0 = n0;
     sa.mode = 1;
-    PD_HIP(c, pd::sweep(c->Nc, sa, pc, st), "coarse sweep");
+    PD_HIP(c, run_sweep(), "coarse sweep");
     PD_HIP(c, hipEventRecord(ev[2], st), "event");
     PD_HIP(c, hipMemcpyAsync(c->hred, c->red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
     PD_HIP(c, hipStreamSynchronize(st), "sync");
