@@ -21,9 +21,8 @@
  * (Section 4), by the second-order semi-implicit backward difference
  * formula (SBDF2) started in every slice with one SBDF1 step (Section 4:
  * multistep methods restart in every slice).  Coarse propagator: same
- * scheme on an N_C grid with step dt_coarse (Section 3.2 "reduced spatial
- * resolution, along with a larger time step"; Section 4 Fourier
- * re-sampling between the grids).
+ * scheme on an N_C grid with step dt_coarse (Section 3.2: coarsening in
+ * space and time; Section 4: Fourier re-sampling between the grids).
  *
  * Conventions for every call:
  *  - returns a pd_status; no C++ exception crosses the ABI;
@@ -127,13 +126,13 @@ pd_status pd_set_initial_dev(pd_ctx* ctx, const void* d_b0, void* hip_stream);
 
 /* Fine propagator F over one slice for `batch` independent fields:
    out[f] = F(in[f]) from time t0[f] (host array) to t0[f] + dT with dt_fine
-   (n_f = dT/dt_fine steps, Section 3 "fine method").  in and out: device,
+   (n_f = dT/dt_fine steps; the fine propagator of Section 3).  in and out: device,
    full layout [batch][3][N][N]; they may alias.  Needs pd_set_time. */
 pd_status pd_fine_dev(pd_ctx* ctx, const double* t0, int batch, const void* d_in, void* d_out,
                       void* hip_stream);
 /* Coarse propagator G over one slice: restrict to the N_coarse box, n_c =
    dT/dt_coarse steps on the N_coarse grid, zero-pad back (Section 4,
-   set_scales re-sampling).  Same arguments as pd_fine_dev. */
+   Fourier re-sampling).  Same arguments as pd_fine_dev. */
 pd_status pd_coarse_dev(pd_ctx* ctx, const double* t0, int batch, const void* d_in, void* d_out,
                         void* hip_stream);
 /* Any number of steps of size dt on the fine grid from t0[f] (no slice

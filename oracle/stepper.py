@@ -16,10 +16,11 @@ SBDF1 (backward/forward Euler) step:
 
 with t_j = t0 + j dt evaluated as a product, never accumulated.
 
-Coarse grids (Section 3.2, "reduced spatial resolution, along with a larger
-time step"; Section 4, Fourier re-sampling between the two solvers): a field
-moves to an N_C grid by keeping the coefficients inside the N_C 2/3 box, and
-back by zero padding.
+Coarse grids (Section 3.2 lists coarsening in space together with a larger
+step as a coarse strategy, and Section 5.2 adopts it; Section 4 moves fields
+between the two solvers by Fourier re-sampling): a field moves to an N_C grid
+by keeping the coefficients inside the N_C 2/3 box, and back by zero
+padding.
 """
 from __future__ import annotations
 
@@ -82,8 +83,8 @@ class SliceSolver:
 
     ``N_solver`` is the grid it steps on; fields come in and go out on the
     fine grid ``N`` (restricted on entry, prolonged on exit when the grids
-    differ, Section 4 pseudo-code: set_scales before and after the coarse
-    solve).
+    differ, as the Parareal pseudo-code of Section 4.1 re-samples around each
+    coarse solve).
     """
 
     def __init__(self, flow: str, Rm: float, kz: float, N: int, dT: float,
