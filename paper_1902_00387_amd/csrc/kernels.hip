@@ -93,12 +93,13 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
         w[c][e] = (active && kx >= -K && kx <= K) ? B[(c * M + r) * M + kx + K] : czero();
       }
   } else {
+    // all three components' loads are issued before the first transform
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int e = 0; e < E; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : czero();
-      fft<N, E, -1>(w[c], s, j, tw);
-    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, tw);
     const double sc = 1.0 / ((double)N * (double)N);
     const double dt = pb.dt, kz = pb.kz;
 #pragma unroll
@@ -150,77 +151,94 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 
 // Column phase of the columns [x0, x0 + TX) of one field at time t, by the
 // whole workgroup (TX = blockDim / T groups; group g owns column x0 + g).
-// Rows are staged through an LDS tile (pitch TX + 1) so that global loads
-// and stores run along x, TX values at a time; each group transforms its
-// column in registers with its own LDS span for the exchanges.
+// The three components' M x TX row blocks are staged through LDS tiles
+// (pitch TX + 1) so that global loads and stores run along x and all three
+// are in flight at once; once every group holds its column in registers the
+// tile memory doubles as the groups' FFT exchange spans.
 template <int N, int E>
-__device__ __forceinline__ void col_tile(int x0, cplx* tile, cplx* spans,
-                                         const cplx* __restrict__ T1, cplx* __restrict__ T2,
-                                         const cplx* __restrict__ tw, const FlowPhase& fp) {
+__device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restrict__ T1,
+                                         cplx* __restrict__ T2, const cplx* __restrict__ tw,
+                                         const FlowPhase& fp) {
   using G = Geo<N, E>;
   constexpr int T = G::T, K = G::K, M = G::M;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int TX = nthr / T < N ? nthr / T : N;
   const int TP = TX + 1;
+  const int TS = M * TP;  // one component's tile
   const int g = tid / T, j = tid % T;
   const int x = x0 + g;
   const bool active = g < TX && x < N;
-  cplx* s = spans + (g < TX ? g : 0) * G::SPAN;
+  cplx* s = tile + (g < TX ? g : 0) * G::SPAN;
+  for (int i = tid; i < 3 * M * TX; i += nthr) {
+    const int c = i / (M * TX), rem = i - c * (M * TX);
+    const int r = rem / TX, cc = rem - r * TX;
+    tile[c * TS + r * TP + cc] = (x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : czero();
+  }
+  __syncthreads();
   cplx w[3][E];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    for (int i = tid; i < M * TX; i += nthr) {
-      const int r = i / TX, cc = i - r * TX;
-      tile[r * TP + cc] = (x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : czero();
-    }
-    __syncthreads();
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = signed_k(j + T * e, N);
-      w[c][e] = (active && ky >= -K && ky <= K) ? tile[(ky + K) * TP + g] : czero();
+      w[c][e] = (active && ky >= -K && ky <= K) ? tile[c * TS + (ky + K) * TP + g] : czero();
     }
-    if (g < TX) fft<N, E, 1>(w[c], s, j, tw);
-    __syncthreads();
-  }
-  // E = u x b at (x, y_e)
-  const int xa = active ? x : 0;
-  const double cx = tw[xa].re, sx = -tw[xa].im;
-  const double cxp = cx * fp.cpx - sx * fp.spx;   // cos(x + px)
-  const double sxp = sx * fp.cpx + cx * fp.spx;   // sin(x + px)
+  __syncthreads();
+  if (g < TX) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int m = j + T * e;
-    const double cy = tw[m].re, sy = -tw[m].im;
-    const double cyp = cy * fp.cpy - sy * fp.spy;  // cos(y + py)
-    const double syp = sy * fp.cpy + cy * fp.spy;  // sin(y + py)
-    const double ux = fp.amp * cyp, uy = fp.amp * sxp, uz = fp.amp * (cxp + syp);
-    const cplx bx = w[0][e], by = w[1][e], bz = w[2][e];
-    w[0][e] = csub(cscale(bz, uy), cscale(by, uz));
-    w[1][e] = csub(cscale(bx, uz), cscale(bz, ux));
-    w[2][e] = csub(cscale(by, ux), cscale(bx, uy));
-  }
+    for (int c = 0; c < 3; ++c) fft<N, E, 1>(w[c], s, j, tw);
+    // E = u x b at (x, y_e)
+    const int xa = active ? x : 0;
+    const double cx = tw[xa].re, sx = -tw[xa].im;
+    const double cxp = cx * fp.cpx - sx * fp.spx;   // cos(x + px)
+    const double sxp = sx * fp.cpx + cx * fp.spx;   // sin(x + px)
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (g < TX) {
-      fft<N, E, -1>(w[c], s, j, tw);
+    for (int e = 0; e < E; ++e) {
+      const int m = j + T * e;
+      const double cy = tw[m].re, sy = -tw[m].im;
+      const double cyp = cy * fp.cpy - sy * fp.spy;  // cos(y + py)
+      const double syp = sy * fp.cpy + cy * fp.spy;  // sin(y + py)
+      const double ux = fp.amp * cyp, uy = fp.amp * sxp, uz = fp.amp * (cxp + syp);
+      const cplx bx = w[0][e], by = w[1][e], bz = w[2][e];
+      w[0][e] = csub(cscale(bz, uy), cscale(by, uz));
+      w[1][e] = csub(cscale(bx, uz), cscale(bz, ux));
+      w[2][e] = csub(cscale(by, ux), cscale(bx, uy));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, tw);
+  }
+  __syncthreads();
+  if (g < TX) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int ky = signed_k(j + T * e, N);
-        if (ky >= -K && ky <= K) tile[(ky + K) * TP + g] = w[c][e];
+        if (ky >= -K && ky <= K) tile[c * TS + (ky + K) * TP + g] = w[c][e];
       }
-    }
-    __syncthreads();
-    for (int i = tid; i < M * TX; i += nthr) {
-      const int r = i / TX, cc = i - r * TX;
-      if (x0 + cc < N) T2[(c * M + r) * N + x0 + cc] = tile[r * TP + cc];
-    }
-    __syncthreads();
   }
+  __syncthreads();
+  for (int i = tid; i < 3 * M * TX; i += nthr) {
+    const int c = i / (M * TX), rem = i - c * (M * TX);
+    const int r = rem / TX, cc = rem - r * TX;
+    if (x0 + cc < N) T2[(c * M + r) * N + x0 + cc] = tile[c * TS + r * TP + cc];
+  }
+  __syncthreads();
 }
 
+// Column groups of a workgroup of `lanes` lanes, and the LDS entries
+// col_tile needs: three component tiles, at least as large as the groups'
+// FFT spans they double as.
+template <int N, int E>
+__host__ __device__ constexpr int col_groups(int lanes) {
+  return lanes / Geo<N, E>::T < N ? lanes / Geo<N, E>::T : N;
+}
 template <int N, int E>
 __host__ __device__ constexpr int tile_elems(int lanes) {
-  return Geo<N, E>::M * ((lanes / Geo<N, E>::T < N ? lanes / Geo<N, E>::T : N) + 1);
+  const int tx = col_groups<N, E>(lanes);
+  const int tiles = 3 * Geo<N, E>::M * (tx + 1);
+  const int spans = tx * Geo<N, E>::SPAN;
+  return tiles > spans ? tiles : spans;
 }
 
 // ---------------------------------------------------------------------------
@@ -240,16 +258,16 @@ __global__ __launch_bounds__(64) void k_rows(FieldBatch fb, Problem pb, int mode
 }
 
 template <int N>
-__global__ __launch_bounds__(Shape<N>::TXC * (N / Shape<N>::EC)) void k_cols(FieldBatch fb,
-                                                                           Problem pb, int step) {
+__global__ __launch_bounds__(Shape<N>::TXC * (N / Shape<N>::EC))
+__attribute__((amdgpu_waves_per_eu(N <= 256 ? 4 : 2))) void k_cols(FieldBatch fb, Problem pb,
+                                                                 int step) {
   constexpr int E = Shape<N>::EC, TX = Shape<N>::TXC;
   using G = Geo<N, E>;
   __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
-  __shared__ cplx spans[TX * G::SPAN];
   const size_t f = blockIdx.y;
   const size_t rows = (size_t)3 * G::M * N;
   const FlowPhase fp = flow_phase(pb, fb.t0[f] + step * pb.dt);
-  col_tile<N, E>(blockIdx.x * TX, tile, spans, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
+  col_tile<N, E>(blockIdx.x * TX, tile, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,11 +282,13 @@ struct SingleLds {
   using G = GR;
   static constexpr int NGR = L / GR::T, NGC = L / GC::T;
   static constexpr int TILE = tile_elems<N, Shape<N>::ESC>(L);
-  static constexpr int SPANS = (NGR > NGC ? NGR : NGC) * GR::SPAN;
+  static constexpr int SPANS = NGR * GR::SPAN;
+  // the row phase's spans and the column phase's tiles never coexist
+  static constexpr int LDS = TILE > SPANS ? TILE : SPANS;
 };
 
 template <int N>
-__device__ __forceinline__ void propagate_wg(cplx* tile, cplx* spans, cplx* B, cplx* H, cplx* T1,
+__device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* T1,
                                              cplx* T2, const cplx* tw, const Problem& pb,
                                              double t0, int nsteps) {
   using S = SingleLds<N>;
@@ -277,13 +297,15 @@ __device__ __forceinline__ void propagate_wg(cplx* tile, cplx* spans, cplx* B, c
   constexpr int TX = NGC < N ? NGC : N;
   const int tid = threadIdx.x;
   const int rg = tid / TR, rj = tid % TR;
+  cplx* spans = lds;
+  cplx* tile = lds;
   for (int r0 = 0; r0 < M; r0 += NGR)
     row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb, 0,
                      false);
   __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
     const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
-    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC>(x0, tile, spans, T1, T2, tw, fp);
+    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC>(x0, tile, T1, T2, tw, fp);
     const int mode = step == 0 ? 1 : 2;
     const bool last = step == nsteps - 1;
     for (int r0 = 0; r0 < M; r0 += NGR)
@@ -296,11 +318,10 @@ __device__ __forceinline__ void propagate_wg(cplx* tile, cplx* spans, cplx* B, c
 template <int N>
 __global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Problem pb, int nsteps) {
   using S = SingleLds<N>;
-  __shared__ cplx tile[S::TILE];
-  __shared__ cplx spans[S::SPANS];
+  __shared__ cplx lds[S::LDS];
   const size_t f = blockIdx.x;
   const size_t box = (size_t)3 * S::GR::M * S::GR::M, rows = (size_t)3 * S::GR::M * N;
-  propagate_wg<N>(tile, spans, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows,
+  propagate_wg<N>(lds, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows,
                   fb.tw, pb, fb.t0[f], nsteps);
 }
 
@@ -317,8 +338,7 @@ __global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Proble
 template <int NC>
 __global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem pb) {
   using S = SingleLds<NC>;
-  __shared__ cplx tile[S::TILE];
-  __shared__ cplx spans[S::SPANS];
+  __shared__ cplx lds[S::LDS];
   __shared__ double rs[2][Shape<NC>::LANES];
   constexpr int Mc = S::GR::M, Kc = S::GR::K;
   const int M = a.M, K = (a.M - 1) / 2;
@@ -331,7 +351,7 @@ __global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem
       a.Bc[i] = Un[(c * M + rr + K - Kc) * M + cc + K - Kc];
     }
     __syncthreads();
-    propagate_wg<NC>(tile, spans, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, n * a.dT, a.nsteps);
+    propagate_wg<NC>(lds, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, n * a.dT, a.nsteps);
     cplx* Un1 = a.U + (n + 1) * fbox;
     cplx* Go = a.Gold + n * fbox;
     const cplx* Fn = a.Fo + n * fbox;
