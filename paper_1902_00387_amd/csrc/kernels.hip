@@ -469,7 +469,17 @@ __global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem 
     __syncthreads();
     const double t0 = n * a.dT;
     for (int step = 0; step < a.nsteps; ++step) {
-      const FlowModes fm = flow_modes(pb, t0 + step * dt);
+      FlowModes fm;
+      if (a.ftab != nullptr && pb.tdep) {
+        const double* ft = a.ftab + 4 * ((size_t)n * a.nsteps + step);
+        const double h = 0.5 * pb.amp;
+        fm.ap = {h * ft[0], h * ft[1]};
+        fm.am = {h * ft[0], -h * ft[1]};
+        fm.bp = {h * ft[2], h * ft[3]};
+        fm.bm = {h * ft[2], -h * ft[3]};
+      } else {
+        fm = flow_modes(pb, t0 + step * dt);
+      }
       cplx bn[CONV_MPL][3];
 #pragma unroll
       for (int m = 0; m < CONV_MPL; ++m) {

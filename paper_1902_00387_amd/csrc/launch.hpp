@@ -37,6 +37,8 @@ struct SweepArgs {
   cplx *Bc, *Hc, *T1c, *T2c;  // coarse workspaces
   const cplx* twc;    // coarse twiddles
   double* red;        // [2] defect sums (may be null)
+  const double* ftab; // [P][nsteps][4] cos(py), sin(py), cos(px), sin(px) of the
+                      // flow phases at every coarse step time (time-dependent flow)
   double dT;          // slice length
   int M;              // fine box width
   int P, n0;          // slices, first slice swept

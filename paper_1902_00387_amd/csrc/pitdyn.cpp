@@ -120,6 +120,7 @@ struct pd_ctx {
   DevBuf Uprev, t0s;                   // defect copy, slice start times
   DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
   DevBuf red, flag;                    // reduction outputs, box-check flag
+  DevBuf ftab;                         // flow phases at every coarse step time
   DevBuf wB, wH, wT1, wT2, wt0;        // workspaces of the propagator calls
   double* hred = nullptr;              // pinned host copy of red
 
@@ -281,6 +282,7 @@ void pd_destroy(pd_ctx* c) {
     c->tw.release(); c->twc.release(); c->U.release(); c->Fo.release(); c->Gold.release();
     c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
     c->Bc.release(); c->Hc.release(); c->T1c.release(); c->T2c.release(); c->red.release();
+    c->ftab.release();
     c->flag.release(); c->wB.release(); c->wH.release(); c->wT1.release(); c->wT2.release();
     c->wt0.release();
   }
@@ -376,6 +378,24 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   PD_HIP(c, c->twc.ensure(sizeof(cplx) * Nc), "alloc");
   PD_HIP(c, hipMemcpy(c->twc.p, twc.data(), sizeof(cplx) * Nc, hipMemcpyHostToDevice), "copy");
   PD_HIP(c, hipMemset(c->U.p, 0, box * (P + 1)), "memset");
+  // phases of the time-dependent flow at the coarse step times t = n dT + j dt_c:
+  // (cos py, sin py, cos px, sin px) with px = cos t, py = sin t
+  c->ftab.release();
+  if ((size_t)P * nc <= ((size_t)1 << 24)) {
+    std::vector<double> ft((size_t)4 * P * nc);
+    for (int n = 0; n < P; ++n)
+      for (int j = 0; j < nc; ++j) {
+        const double t = n * dT + j * dtc;
+        const double px = std::cos(t), py = std::sin(t);
+        double* q = &ft[4 * ((size_t)n * nc + j)];
+        q[0] = std::cos(py);
+        q[1] = std::sin(py);
+        q[2] = std::cos(px);
+        q[3] = std::sin(px);
+      }
+    PD_HIP(c, c->ftab.ensure(ft.size() * sizeof(double)), "alloc");
+    PD_HIP(c, hipMemcpy(c->ftab.p, ft.data(), ft.size() * sizeof(double), hipMemcpyHostToDevice), "copy");
+  }
   c->have_time = true;
   return PD_OK;
 }
@@ -477,6 +497,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   sa.T2c = c->T2c.as<cplx>();
   sa.twc = c->twc.as<cplx>();
   sa.red = c->red.as<double>();
+  sa.ftab = c->ftab.as<double>();
   sa.dT = c->dT;
   sa.M = c->M;
   sa.P = P;
