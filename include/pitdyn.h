@@ -169,6 +169,40 @@ pd_status pd_slice_norms(const pd_ctx* ctx, double* norms);
    growth rates without naming an estimator; this is the reading used). */
 pd_status pd_growth_rate(const pd_ctx* ctx, double* gamma);
 
+/* ---- Many independent problems in one batch -------------------------------
+ * Parareal (Section 3) for many (flow, Rm, kz, N) instances of uneven size at
+ * once on one GPU.  Instances of equal (flow, N, fine steps per slice) share
+ * one batched fine sweep a Parareal iteration; the serial coarse sweeps of all
+ * instances run concurrently (one workgroup each, convolution form: the
+ * coarse box is held in LDS when N_coarse <= 64 and in global memory above);
+ * one iteration of the whole batch is captured once in a HIP graph and
+ * replayed.  Each instance stops when its own defect reaches tol. */
+typedef struct pd_batch pd_batch;
+
+pd_status pd_batch_create(pd_batch** out, int hip_device);
+void pd_batch_destroy(pd_batch* b);
+const char* pd_batch_last_error(const pd_batch* b);
+/* Add one instance: the arguments of pd_set_problem and pd_set_time plus its
+   initial field (host, full layout [3][N][N], copied).  *id receives its
+   index.  At most 4096 instances; at most 65535 slices of one grid size. */
+pd_status pd_batch_add(pd_batch* b, pd_flow flow, double Rm, double kz, int N, double T,
+                       int n_slices, double dt_fine, double dt_coarse, int N_coarse,
+                       const double* b0, int* id);
+/* Run Parareal on every instance from its initial field until its sigma <=
+   tol or max_iter iterations (tol = 0: exactly max_iter).  use_graph != 0
+   replays one captured HIP graph per iteration; 0 launches eagerly (same
+   kernels, same results).  PD_NOT_CONVERGED if some instance did not reach
+   tol; PD_EUNSTABLE if some instance went non-finite. */
+pd_status pd_batch_run(pd_batch* b, double tol, int max_iter, int use_graph);
+/* Report of one instance (k_con, sigma history; t_total_s is the whole
+   batch's wall clock) and its growth rate (as pd_growth_rate; gamma may be
+   NULL). */
+pd_status pd_batch_result(const pd_batch* b, int id, pd_report* rep, double* gamma);
+/* Slice states U_n of one instance, full layout [P+1][3][N][N], host. */
+pd_status pd_batch_get_slices(const pd_batch* b, int id, double* out);
+/* Wall-clock seconds of the last pd_batch_run. */
+pd_status pd_batch_time(const pd_batch* b, double* seconds);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,8 @@ SYMBOLS = [
     "pd_set_time", "pd_set_path", "pd_set_coarse_form", "pd_set_initial", "pd_set_initial_dev", "pd_fine_dev",
     "pd_coarse_dev", "pd_steps_dev", "pd_parareal", "pd_get_slices", "pd_get_slices_dev",
     "pd_slice_norms", "pd_growth_rate", "pd_profile_fine",
+    "pd_batch_create", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_add",
+    "pd_batch_run", "pd_batch_result", "pd_batch_get_slices", "pd_batch_time",
 ]
 
 
@@ -94,6 +96,14 @@ def _load():
         "pd_slice_norms": ([vp, dp], i),
         "pd_growth_rate": ([vp, dp], i),
         "pd_profile_fine": ([vp, i, dp], i),
+        "pd_batch_create": ([C.POINTER(vp), i], i),
+        "pd_batch_destroy": ([vp], None),
+        "pd_batch_last_error": ([vp], C.c_char_p),
+        "pd_batch_add": ([vp, i, d, d, i, d, i, d, d, i, dp, C.POINTER(i)], i),
+        "pd_batch_run": ([vp, d, i, i], i),
+        "pd_batch_result": ([vp, i, C.POINTER(Report), dp], i),
+        "pd_batch_get_slices": ([vp, i, dp], i),
+        "pd_batch_time": ([vp, dp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -249,3 +259,72 @@ class Context:
         g = C.c_double()
         self._ok(lib.pd_growth_rate(self._h, C.byref(g)))
         return g.value
+
+
+class Batch:
+    """Many independent Parareal problems of uneven size run together."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = lib.pd_batch_create(C.byref(h), device)
+        if st != OK:
+            raise PitdynError(st, "pd_batch_create failed")
+        self._h = h
+        self.shapes = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _ok(self, st, allow=(OK,)):
+        if st not in allow:
+            raise PitdynError(st, lib.pd_batch_last_error(self._h).decode())
+        return st
+
+    def add(self, flow, Rm, kz, N, T, n_slices, dt_fine, dt_coarse, N_coarse, b0) -> int:
+        f = FLOWS[flow] if isinstance(flow, str) else int(flow)
+        a = np.ascontiguousarray(np.asarray(b0, dtype=np.complex128))
+        if a.shape != (3, N, N):
+            raise ValueError(f"initial field must be [3, {N}, {N}]")
+        i = C.c_int()
+        self._ok(lib.pd_batch_add(self._h, f, float(Rm), float(kz), int(N), float(T), int(n_slices),
+                                  float(dt_fine), float(dt_coarse), int(N_coarse),
+                                  _dptr(a.view(np.float64)), C.byref(i)))
+        self.shapes.append((int(n_slices), int(N)))
+        return i.value
+
+    def run(self, tol: float, max_iter: int, use_graph: bool = True) -> int:
+        return self._ok(lib.pd_batch_run(self._h, float(tol), int(max_iter), int(bool(use_graph))),
+                        allow=(OK, NOT_CONVERGED))
+
+    def result(self, i: int):
+        rep = Report()
+        g = C.c_double()
+        self._ok(lib.pd_batch_result(self._h, int(i), C.byref(rep), C.byref(g)))
+        d = rep.as_dict()
+        d["growth_rate"] = g.value
+        return d
+
+    def slices(self, i: int) -> np.ndarray:
+        P, N = self.shapes[i]
+        out = np.empty((P + 1, 3, N, N), np.complex128)
+        self._ok(lib.pd_batch_get_slices(self._h, int(i), _dptr(out.view(np.float64))))
+        return out
+
+    def seconds(self) -> float:
+        t = C.c_double()
+        self._ok(lib.pd_batch_time(self._h, C.byref(t)))
+        return t.value

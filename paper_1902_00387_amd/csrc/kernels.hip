@@ -249,12 +249,16 @@ __global__ __launch_bounds__(64) void k_rows(FieldBatch fb, Problem pb, int mode
   using G = Geo<N, E>;
   constexpr int RPW = 64 / G::T;
   __shared__ cplx sm[RPW * G::SPAN];
+  if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
   const int g = threadIdx.x / G::T, j = threadIdx.x % G::T;
   const int r = blockIdx.x * RPW + g;
-  const size_t f = blockIdx.y;
+  const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
   const size_t box = (size_t)3 * G::M * G::M, rows = (size_t)3 * G::M * N;
+  Problem p = pb;
+  if (fb.fRm != nullptr) p.Rm = fb.fRm[f];
+  if (fb.fkz != nullptr) p.kz = fb.fkz[f];
   row_phase<N, E>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
-                  fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, pb, mode, last != 0);
+                  fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, p, mode, last != 0);
 }
 
 template <int N>
@@ -264,7 +268,8 @@ __attribute__((amdgpu_waves_per_eu(N <= 256 ? 4 : 2))) void k_cols(FieldBatch fb
   constexpr int E = Shape<N>::EC, TX = Shape<N>::TXC;
   using G = Geo<N, E>;
   __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
-  const size_t f = blockIdx.y;
+  if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
+  const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
   const size_t rows = (size_t)3 * G::M * N;
   const FlowPhase fp = flow_phase(pb, fb.t0[f] + step * pb.dt);
   col_tile<N, E>(blockIdx.x * TX, tile, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
@@ -319,10 +324,14 @@ template <int N>
 __global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Problem pb, int nsteps) {
   using S = SingleLds<N>;
   __shared__ cplx lds[S::LDS];
-  const size_t f = blockIdx.x;
+  if (fb.count != nullptr && (int)blockIdx.x >= *fb.count) return;
+  const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.x] : (size_t)blockIdx.x;
   const size_t box = (size_t)3 * S::GR::M * S::GR::M, rows = (size_t)3 * S::GR::M * N;
+  Problem p = pb;
+  if (fb.fRm != nullptr) p.Rm = fb.fRm[f];
+  if (fb.fkz != nullptr) p.kz = fb.fkz[f];
   propagate_wg<N>(lds, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows,
-                  fb.tw, pb, fb.t0[f], nsteps);
+                  fb.tw, p, fb.t0[f], nsteps);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,9 +447,8 @@ constexpr int CONV_MPL = (CONV_MMAX * CONV_MMAX + CONV_LANES - 1) / CONV_LANES; 
 
 // One workgroup runs the coarse sweep; lane l owns box modes l + CONV_LANES*m
 // (state and history in registers) and reads neighbours from LDS.
-__global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem pb, int Mc) {
-  __shared__ cplx bs[3 * CONV_MMAX * CONV_MMAX];
-  __shared__ double rs[2][CONV_LANES];
+__device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem& pb, int Mc,
+                                               cplx* bs, double (*rs)[CONV_LANES]) {
   const int Kc = (Mc - 1) / 2;
   const int nbox = Mc * Mc;
   const int M = a.M, K = (a.M - 1) / 2;
@@ -592,6 +600,178 @@ __global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem 
   }
 }
 
+
+__global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem pb, int Mc) {
+  __shared__ cplx bs[3 * CONV_MMAX * CONV_MMAX];
+  __shared__ double rs[2][CONV_LANES];
+  sweep_conv_lds(a, pb, Mc, bs, rs);
+}
+
+// Defect sums |U_P - Uprev|^2, |U_P|^2 of one sweep, fixed-order tree.
+__device__ __forceinline__ void defect_sums(const SweepArgs& a, double (*rs)[CONV_LANES]) {
+  const int M = a.M;
+  const size_t fbox = (size_t)3 * M * M;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const cplx* UP = a.U + (size_t)a.P * fbox;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = tid; i < (int)fbox; i += nt) {
+    const cplx d = csub(UP[i], a.Uprev[i]);
+    s0 += d.re * d.re + d.im * d.im;
+    s1 += UP[i].re * UP[i].re + UP[i].im * UP[i].im;
+  }
+  rs[0][tid] = s0;
+  rs[1][tid] = s1;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      rs[0][tid] += rs[0][tid + w];
+      rs[1][tid] += rs[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.red[0] = rs[0][0];
+    a.red[1] = rs[1][0];
+  }
+}
+
+// Coarse sweep for a box too large for LDS: the state is double-buffered in
+// the job's global buffers (Bc, T1c) and the history lives in Hc; every lane
+// steps the modes i = tid, tid + blockDim, ... of the box, reading the
+// neighbours of the previous buffer.  Same arithmetic as sweep_conv_lds.
+__device__ __forceinline__ void sweep_conv_global(const SweepArgs& a, const Problem& pb, int Mc,
+                                                  double (*rs)[CONV_LANES]) {
+  const int Kc = (Mc - 1) / 2;
+  const int nbox = Mc * Mc;
+  const int M = a.M, K = (a.M - 1) / 2;
+  const size_t fbox = (size_t)3 * M * M;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double kz = pb.kz, dt = pb.dt;
+  cplx* buf[2] = {a.Bc, a.T1c};
+  cplx* Hg = a.Hc;
+  for (int n = a.n0; n < a.P; ++n) {
+    const cplx* Un = a.U + n * fbox;
+    for (int i = tid; i < 3 * nbox; i += nt) {
+      const int c = i / nbox, rem = i - c * nbox;
+      const int ky = rem / Mc - Kc, kx = rem % Mc - Kc;
+      buf[0][i] = Un[(c * M + ky + K) * M + kx + K];
+    }
+    __syncthreads();
+    const double t0 = n * a.dT;
+    for (int step = 0; step < a.nsteps; ++step) {
+      FlowModes fm;
+      if (a.ftab != nullptr && pb.tdep) {
+        const double* ft = a.ftab + 4 * ((size_t)n * a.nsteps + step);
+        const double h = 0.5 * pb.amp;
+        fm.ap = {h * ft[0], h * ft[1]};
+        fm.am = {h * ft[0], -h * ft[1]};
+        fm.bp = {h * ft[2], h * ft[3]};
+        fm.bm = {h * ft[2], -h * ft[3]};
+      } else {
+        fm = flow_modes(pb, t0 + step * dt);
+      }
+      const cplx* bs = buf[step & 1];
+      cplx* bo = buf[(step + 1) & 1];
+      for (int i = tid; i < nbox; i += nt) {
+        const int ky = i / Mc - Kc, kx = i % Mc - Kc;
+        cplx e[3] = {czero(), czero(), czero()};
+        if (ky - 1 >= -Kc) {
+          const int si = (ky - 1 + Kc) * Mc + kx + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx aby = cmul(fm.ap, by);
+          e[0] = cadd(e[0], mul_i<1>(aby));
+          e[1] = csub(e[1], cadd(mul_i<1>(cmul(fm.ap, bx)), cmul(fm.ap, bz)));
+          e[2] = cadd(e[2], aby);
+        }
+        if (ky + 1 <= Kc) {
+          const int si = (ky + 1 + Kc) * Mc + kx + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx aby = cmul(fm.am, by);
+          e[0] = csub(e[0], mul_i<1>(aby));
+          e[1] = cadd(e[1], csub(mul_i<1>(cmul(fm.am, bx)), cmul(fm.am, bz)));
+          e[2] = cadd(e[2], aby);
+        }
+        if (kx - 1 >= -Kc) {
+          const int si = (ky + Kc) * Mc + kx - 1 + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx bbx = cmul(fm.bp, bx);
+          e[0] = csub(e[0], cadd(mul_i<1>(cmul(fm.bp, bz)), cmul(fm.bp, by)));
+          e[1] = cadd(e[1], bbx);
+          e[2] = cadd(e[2], mul_i<1>(bbx));
+        }
+        if (kx + 1 <= Kc) {
+          const int si = (ky + Kc) * Mc + kx + 1 + Kc;
+          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const cplx bbx = cmul(fm.bm, bx);
+          e[0] = cadd(e[0], csub(mul_i<1>(cmul(fm.bm, bz)), cmul(fm.bm, by)));
+          e[1] = cadd(e[1], bbx);
+          e[2] = csub(e[2], mul_i<1>(bbx));
+        }
+        const double kxd = kx, kyd = ky;
+        const double aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / pb.Rm;
+        cplx nl[3];
+        nl[0] = mul_i<1>(csub(cscale(e[2], kyd), cscale(e[1], kz)));
+        nl[1] = mul_i<1>(csub(cscale(e[0], kz), cscale(e[2], kxd)));
+        nl[2] = mul_i<1>(csub(cscale(e[1], kxd), cscale(e[0], kyd)));
+        const double inv = step == 0 ? 1.0 / (1.0 + aa) : 1.0 / (1.5 + aa);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const cplx b = bs[c * nbox + i];
+          cplx bn;
+          if (step == 0) {
+            bn = cscale(cadd(b, cscale(nl[c], dt)), inv);
+          } else {
+            bn = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), Hg[c * nbox + i]), inv);
+          }
+          Hg[c * nbox + i] = csub(cscale(b, -0.5), cscale(nl[c], dt));
+          bo[c * nbox + i] = bn;
+        }
+      }
+      __syncthreads();
+    }
+    const cplx* bfin = buf[a.nsteps & 1];
+    cplx* Un1 = a.U + (n + 1) * fbox;
+    cplx* Go = a.Gold + n * fbox;
+    const cplx* Fn = a.Fo + n * fbox;
+    for (int i = tid; i < (int)fbox; i += nt) {
+      const int c = i / (M * M), r = (i / M) % M, cc = i % M;
+      const int dr = r - K, dc = cc - K;
+      cplx g = czero();
+      if (dr >= -Kc && dr <= Kc && dc >= -Kc && dc <= Kc) g = bfin[c * nbox + (dr + Kc) * Mc + dc + Kc];
+      if (a.mode == 0) {
+        Un1[i] = g;
+      } else {
+        Un1[i] = cadd(Fn[i], csub(g, Go[i]));
+      }
+      Go[i] = g;
+    }
+    __syncthreads();
+  }
+  if (a.mode != 0 && a.red != nullptr) defect_sums(a, rs);
+}
+
+template <bool LDS_RESIDENT>
+__global__ __launch_bounds__(CONV_LANES) void k_sweep_conv_jobs(const SweepJob* jobs, int njobs) {
+  __shared__ double rs[2][CONV_LANES];
+  if ((int)blockIdx.x >= njobs) return;
+  const SweepJob& jb = jobs[blockIdx.x];
+  if (!jb.active) return;
+  // keep U^{k-1}_P for the defect before the sweep overwrites it
+  if (jb.a.mode != 0 && jb.a.Uprev != nullptr) {
+    const size_t fbox = (size_t)3 * jb.a.M * jb.a.M;
+    const cplx* UP = jb.a.U + (size_t)jb.a.P * fbox;
+    cplx* Up = const_cast<cplx*>(jb.a.Uprev);
+    for (int i = threadIdx.x; i < (int)fbox; i += blockDim.x) Up[i] = UP[i];
+    __syncthreads();
+  }
+  if constexpr (LDS_RESIDENT) {
+    __shared__ cplx bs[3 * CONV_MMAX * CONV_MMAX];
+    sweep_conv_lds(jb.a, jb.pb, jb.Mc, bs, rs);
+  } else {
+    sweep_conv_global(jb.a, jb.pb, jb.Mc, rs);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Layout conversion, box check, copies, norms.
 __global__ void k_pack(const cplx* __restrict__ full, cplx* __restrict__ box, int N, int M,
@@ -636,6 +816,19 @@ __global__ void k_check_box(const cplx* __restrict__ full, int N, int K, size_t 
       if (v.re != 0.0 || v.im != 0.0) flag[0] = 1;
     }
   }
+}
+
+// Fo[f] = U[uidx[f]] for the active fields f = map[row], row < *count.
+__global__ __launch_bounds__(256) void k_gather(const cplx* __restrict__ U, cplx* __restrict__ Fo,
+                                                const int* __restrict__ uidx,
+                                                const int* __restrict__ map,
+                                                const int* __restrict__ count, size_t box) {
+  if ((int)blockIdx.y >= *count) return;
+  const int f = map[blockIdx.y];
+  const cplx* src = U + (size_t)uidx[f] * box;
+  cplx* dst = Fo + (size_t)f * box;
+  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < box; i += (size_t)gridDim.x * 256)
+    dst[i] = src[i];
 }
 
 // per-field squared two-norm, fixed-order reduction (one workgroup a field)
@@ -761,6 +954,15 @@ hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t
   return hipGetLastError();
 }
 
+hipError_t sweep_conv_jobs(const SweepJob* d_jobs, int njobs, bool lds_resident, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  if (lds_resident)
+    hipLaunchKernelGGL(k_sweep_conv_jobs<true>, dim3(njobs), dim3(CONV_LANES), 0, st, d_jobs, njobs);
+  else
+    hipLaunchKernelGGL(k_sweep_conv_jobs<false>, dim3(njobs), dim3(CONV_LANES), 0, st, d_jobs, njobs);
+  return hipGetLastError();
+}
+
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
   switch (Nc) {
     case 16: return launch_sweep<16>(a, pb, st);
@@ -794,6 +996,14 @@ hipError_t unpack(const cplx* box, cplx* full, int N, int M, size_t nfields, hip
 hipError_t check_box(const cplx* full, int N, size_t nfields, int* dflag, hipStream_t st) {
   hipLaunchKernelGGL(k_check_box, dim3(grid_for(nfields * 3 * (size_t)N * N)), dim3(256), 0, st,
                      full, N, (N - 1) / 3, nfields, dflag);
+  return hipGetLastError();
+}
+
+hipError_t gather(const cplx* U, cplx* Fo, const int* uidx, const int* map, const int* count,
+                  int rows, size_t box, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  dim3 grid((unsigned)((box + 255) / 256 < 64 ? (box + 255) / 256 : 64), rows);
+  hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, st, U, Fo, uidx, map, count, box);
   return hipGetLastError();
 }
 

@@ -21,29 +21,45 @@ struct Problem {
 
 // A batch of fields stepped together (all of grid size N).
 struct FieldBatch {
-  cplx* B;           // [f][3][M][M] state (in: start value, out: end value)
-  cplx* H;           // [f][3][M][M] SBDF2 history workspace
-  cplx* T1;          // [f][3][M][N] row workspace
-  cplx* T2;          // [f][3][M][N] row workspace
-  const double* t0;  // [f] start time of each field's slice
-  const cplx* tw;    // [N] twiddles e^{-2 pi i m/N}
+  cplx* B = nullptr;           // [f][3][M][M] state (in: start value, out: end value)
+  cplx* H = nullptr;           // [f][3][M][M] SBDF2 history workspace
+  cplx* T1 = nullptr;          // [f][3][M][N] row workspace
+  cplx* T2 = nullptr;          // [f][3][M][N] row workspace
+  const double* t0 = nullptr;  // [f] start time of each field's slice
+  const cplx* tw = nullptr;    // [N] twiddles e^{-2 pi i m/N}
+  // optional (null: use the Problem's scalars / the identity map)
+  const double* fRm = nullptr;  // [f] per-field Rm
+  const double* fkz = nullptr;  // [f] per-field kz
+  const int* map = nullptr;     // [launch row] field index; rows >= *count exit at once
+  const int* count = nullptr;   // device count of active launch rows
 };
 
+struct SweepArgs;
+// One instance's coarse sweep in a batched sweep launch.
+struct SweepJob;
+
 struct SweepArgs {
-  cplx* U;            // [P+1][3][M][M] slice-boundary states (fine, compact)
-  const cplx* Fo;     // [P][3][M][M] fine results F(U^{k-1}_n)
-  cplx* Gold;         // [P][3][M][M] previous coarse results
-  const cplx* Uprev;  // [3][M][M] U^{k-1}_P (defect)
-  cplx *Bc, *Hc, *T1c, *T2c;  // coarse workspaces
-  const cplx* twc;    // coarse twiddles
-  double* red;        // [2] defect sums (may be null)
-  const double* ftab; // [P][nsteps][4] cos(py), sin(py), cos(px), sin(px) of the
+  cplx* U = nullptr;            // [P+1][3][M][M] slice-boundary states (fine, compact)
+  const cplx* Fo = nullptr;     // [P][3][M][M] fine results F(U^{k-1}_n)
+  cplx* Gold = nullptr;         // [P][3][M][M] previous coarse results
+  const cplx* Uprev = nullptr;  // [3][M][M] U^{k-1}_P (defect; the batched sweep fills it)
+  cplx *Bc = nullptr, *Hc = nullptr, *T1c = nullptr, *T2c = nullptr;  // coarse workspaces
+  const cplx* twc = nullptr;    // coarse twiddles
+  double* red = nullptr;        // [2] defect sums (may be null)
+  const double* ftab = nullptr; // [P][nsteps][4] cos(py), sin(py), cos(px), sin(px) of the
                       // flow phases at every coarse step time (time-dependent flow)
   double dT;          // slice length
   int M;              // fine box width
   int P, n0;          // slices, first slice swept
   int nsteps;         // coarse steps per slice
   int mode;           // 0: initial coarse run, 1: correction
+};
+
+struct SweepJob {
+  SweepArgs a;
+  Problem pb;
+  int Mc;      // coarse box width
+  int active;  // 0: skip (instance converged)
 };
 
 hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
@@ -57,11 +73,18 @@ hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
 // same sweep with the explicit term as the exact spectral convolution with the
 // flow's four Fourier modes (N_C <= 64)
 hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
+// many independent coarse sweeps, one workgroup each (convolution form);
+// jobs with Mc <= 45 keep the box in LDS, larger ones in their Bc/T1c/Hc
+// global buffers (3 Mc^2 values each)
+hipError_t sweep_conv_jobs(const SweepJob* d_jobs, int njobs, bool lds_resident, hipStream_t st);
 // full layout [f][3][N][N] <-> compact [f][3][M][M] of the |k| <= (M-1)/2 box
 // (M < box width of N restricts / zero-pads: Fourier re-sampling)
 hipError_t pack(const cplx* full, cplx* box, int N, int M, size_t nfields, hipStream_t st);
 hipError_t unpack(const cplx* box, cplx* full, int N, int M, size_t nfields, hipStream_t st);
 hipError_t check_box(const cplx* full, int N, size_t nfields, int* dflag, hipStream_t st);
 hipError_t norms2(const cplx* x, size_t len, int nfields, double* out, hipStream_t st);
+// Fo[f] = U[uidx[f]] for f = map[row], row < *count (rows = launch rows)
+hipError_t gather(const cplx* U, cplx* Fo, const int* uidx, const int* map, const int* count,
+                  int rows, size_t box, hipStream_t st);
 
 }  // namespace pd
