@@ -71,6 +71,77 @@ def cpu_baseline(budget_s=15.0):
                       f"(serial, {dt:.1f} s)"}
 
 
+def batch_workload(scale=1.0):
+    """Many independent Galloway-Proctor problems of uneven size: 96 at 64^2,
+    96 at 128^2 and 64 at 256^2 (times `scale`), Rm log-uniform in [10, 1000],
+    kz uniform in [0.2, 1.2], T = 32 over 32 slices.  Fine steps per unit time
+    ceil(2 A K / 0.2), coarse grid N/2 with ceil(2 A K_C / 0.4) steps per unit
+    time (A = sqrt(3/2), K = floor((N-1)/3))."""
+    from synthetic import gp_instance_params, initial_field
+    counts = [(64, 96), (128, 96), (256, 64)]
+    specs = []
+    for N, cnt in counts:
+        specs += [N] * max(1, int(round(cnt * scale)))
+    rm, kz = gp_instance_params(len(specs), 300000)
+    A = math.sqrt(1.5)
+    out = []
+    for i, N in enumerate(specs):
+        K, Nc = (N - 1) // 3, N // 2
+        Kc = (Nc - 1) // 3
+        nf = math.ceil(2 * A * K / 0.2)
+        nc = math.ceil(2 * A * Kc / 0.4)
+        out.append(dict(N=N, Nc=Nc, Rm=float(rm[i]), kz=float(kz[i]), T=32.0, P=32,
+                        dtf=1.0 / nf, dtc=1.0 / nc, nf=nf, seed=300000 + i))
+    return out
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+    inst = batch_workload(args.batch_scale)
+    b = pd.Batch(0)
+    for it in inst:
+        b.add("gp", it["Rm"], it["kz"], it["N"], it["T"], it["P"], it["dtf"], it["dtc"], it["Nc"],
+              initial_field(it["N"], it["kz"], it["seed"]))
+    print(f"# batch: {len(inst)} instances", file=sys.stderr, flush=True)
+    st = b.run(TOL, 32, use_graph=True)   # first run builds buffers and captures the graph
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        st = b.run(TOL, 32, use_graph=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    secs = min(times)
+    reps = [b.result(i) for i in range(len(inst))]
+    done_ms = 0.0
+    serial_ms = 0.0
+    for it, r in zip(inst, reps):
+        P, nf, N = it["P"], it["nf"], it["N"]
+        serial_ms += P * nf * N * N
+        for k in range(1, r["iters"] + 1):
+            done_ms += (P - min(k - 1, P - 1)) * nf * N * N
+    kc = [r["k_con"] for r in reps]
+    out = {
+        "metric": "batched instances: serial-equivalent fine mode-steps/sec (Parareal to sigma<=1e-8)",
+        "value": serial_ms / secs, "unit": "mode-steps/s", "n_gpus": 1,
+        "status": st, "seconds": secs, "instances": len(inst),
+        "fine_mode_steps_computed_per_s": done_ms / secs,
+        "k_con": {"min": min(kc), "max": max(kc), "mean": float(np.mean(kc)),
+                  "not_converged": int(sum(1 for k in kc if k < 0))},
+        "growth_rate_range": [float(min(r["growth_rate"] for r in reps)),
+                              float(max(r["growth_rate"] for r in reps))],
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"{len(inst)} GP instances (64^2/128^2/256^2 = 3:3:2), Rm log-U[10,1000], "
+                               "kz U[0.2,1.2], 32 slices, T=32, coarse N/2, tol 1e-8, HIP graph"},
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +150,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the fine-sweep kernels (for profiler runs)")
+    ap.add_argument("--batch", action="store_true",
+                    help="the many-instance workload instead of the single solve")
+    ap.add_argument("--batch-scale", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
@@ -92,6 +166,9 @@ def main():
     from synthetic import initial_field
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch:
+        run_batch(args)
+        return
     dev = torch.device("cuda:0")
     b0 = torch.from_numpy(initial_field(N, KZ, SEED)).to(dev)
     ctx = pd.Context(0)
