@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the many-instance workload instead of the single solve")
     ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
@@ -174,7 +175,15 @@ def main():
     ctx = pd.Context(0)
     ctx.set_problem("gp", RM, KZ, N)
     ctx.set_time(T, P, DT_FINE, DT_COARSE, N_COARSE)
+    ctx.set_path(args.path)
     nf = int(round(T / P / DT_FINE))
+    # launch shapes of the fine step's kernels, picked by timing on this device
+    ctx.set_initial(b0)
+    ctx.parareal(0.0, 0)
+    tuned, tuned_ms = ctx.autotune(10)
+    print(f"# autotune: rows variant {tuned[0]} {pd.variants(N, 0)[tuned[0]]} "
+          f"{tuned_ms[0]*1e3:.1f} us, cols variant {tuned[1]} {pd.variants(N, 1)[tuned[1]]} "
+          f"{tuned_ms[1]*1e3:.1f} us", file=sys.stderr, flush=True)
 
     def solve():
         ctx.set_initial(b0)
@@ -187,8 +196,13 @@ def main():
         ctx.parareal(0.0, 0)
         for _ in range(max(1, args.steps)):
             ctx.profile_fine(20)
+        # a plain device copy of known size (1 GiB read + 1 GiB written), to
+        # calibrate profiler byte counters against
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"kernel_only": True}), flush=True)
+        print(json.dumps({"kernel_only": True, "copy_bytes_each_way": src.numel() * 8}), flush=True)
         return
 
     for _ in range(args.warmup):
@@ -253,6 +267,9 @@ def main():
             "serial_fine_gpu_s": serial_s,
             "speedup_vs_serial_fine_gpu": serial_s / (ms_step * 1e-3),
         },
+        "autotune": {"rows_variant": list(pd.variants(N, 0)[tuned[0]]),
+                     "cols_variant": list(pd.variants(N, 1)[tuned[1]]),
+                     "note": "rows: (values a lane, waves a workgroup); cols: (values a lane, columns a workgroup)"},
         "fine_sweep": {
             "mode_steps_per_s": fine_rate,
             "ms_per_fine_step_all_slices": ms_fstep,
@@ -262,7 +279,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cols<128>" if dominant[0] == "cols" else "k_rows<128>",
+            "kernel": "k_cols<128,%d,%d>" % tuple(pd.variants(N, 1)[tuned[1]]) if dominant[0] == "cols"
+                      else "k_rows<128,%d,%d>" % tuple(pd.variants(N, 0)[tuned[0]]),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -68,7 +68,10 @@ typedef enum {
 typedef enum {
   PD_PATH_AUTO = -1,   /* library chooses                                 */
   PD_PATH_MULTI = 0,   /* two launches per step over all fields and tiles */
-  PD_PATH_SINGLE = 1   /* one workgroup per field runs every step         */
+  PD_PATH_SINGLE = 1,  /* one workgroup per field runs every step         */
+  PD_PATH_MULTI2 = 2   /* two-launch path with the batch halved over two
+                          streams, half a step apart, so column-phase and
+                          row-phase launches overlap                     */
 } pd_path;
 
 typedef enum {
@@ -157,6 +160,27 @@ pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
    row-phase (SBDF2) kernel over `reps` back-to-back launches on the
    context's stream (0 on the single-workgroup path).  HIP events. */
 pd_status pd_profile_fine(pd_ctx* ctx, int reps, double* ms);
+
+/* Launch-shape autotuner for the fine step's two kernels.  The row-phase
+   kernel has variants in values a lane (8 or 4) and waves a workgroup; the
+   column-phase kernel in values a lane and columns a workgroup (which sets
+   its LDS tile).  pd_autotune times every variant of both on this context's
+   slice batch (reps back-to-back launches each, after one warm-up round; the
+   inputs are the current slice states, which are left unchanged), selects the
+   fastest of each process-wide for this N, and returns their indices in
+   chosen[0] (rows), chosen[1] (columns) and their mean launch times in ms[0..1]
+   (either may be NULL).  With cache_path non-NULL the choice is first looked
+   up in that JSON file (key "<gfx arch>|<N>|<n_slices>"; ms = 0 on a hit) and
+   stored there after timing.  Variants give identical results bitwise only
+   with equal values a lane; all agree with the oracle to the parity bar. */
+pd_status pd_autotune(pd_ctx* ctx, int reps, const char* cache_path, int* chosen, double* ms);
+/* Variant table: v = -1 puts the number of variants of `kind` (0 rows,
+   1 columns) for grid N in *a; v >= 0 describes variant v (rows: *a values a
+   lane, *b waves a workgroup; columns: *a values a lane, *b columns a
+   workgroup). */
+pd_status pd_variant_info(int N, int kind, int v, int* a, int* b);
+/* Select launch-shape variants for grid N process-wide (0, 0 = defaults). */
+pd_status pd_select_variant(int N, int rows_v, int cols_v);
 
 /* Slice-boundary states U_n, n = 0..n_slices, full layout [P+1][3][N][N]. */
 pd_status pd_get_slices(const pd_ctx* ctx, double* out);

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libpitdyn.so")
 
 FLOW_NONE, FLOW_ROBERTS, FLOW_GP = 0, 1, 2
 FLOWS = {"none": FLOW_NONE, "roberts": FLOW_ROBERTS, "gp": FLOW_GP}
-PATH_AUTO, PATH_MULTI, PATH_SINGLE = -1, 0, 1
+PATH_AUTO, PATH_MULTI, PATH_SINGLE, PATH_MULTI2 = -1, 0, 1, 2
 COARSE_AUTO, COARSE_FFT, COARSE_CONV = 0, 1, 2
 MAX_ITER = 256
 
@@ -39,6 +39,7 @@ SYMBOLS = [
     "pd_slice_norms", "pd_growth_rate", "pd_profile_fine",
     "pd_batch_create", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_add",
     "pd_batch_run", "pd_batch_result", "pd_batch_get_slices", "pd_batch_time",
+    "pd_autotune", "pd_variant_info", "pd_select_variant",
 ]
 
 
@@ -104,6 +105,9 @@ def _load():
         "pd_batch_result": ([vp, i, C.POINTER(Report), dp], i),
         "pd_batch_get_slices": ([vp, i, dp], i),
         "pd_batch_time": ([vp, dp], i),
+        "pd_autotune": ([vp, i, C.c_char_p, C.POINTER(i), dp], i),
+        "pd_variant_info": ([i, i, i, C.POINTER(i), C.POINTER(i)], i),
+        "pd_select_variant": ([i, i, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -255,10 +259,37 @@ class Context:
         self._ok(lib.pd_profile_fine(self._h, int(reps), _dptr(ms)))
         return float(ms[0]), float(ms[1]), float(ms[2])
 
+    def autotune(self, reps: int = 10, cache_path=None):
+        """Pick the fastest launch shapes of the fine step's kernels for this
+        grid size; returns ((rows variant, cols variant), (ms rows, ms cols))."""
+        ch = (C.c_int * 2)()
+        ms = np.zeros(2, np.float64)
+        cp = cache_path.encode() if cache_path else None
+        self._ok(lib.pd_autotune(self._h, int(reps), cp, ch, _dptr(ms)))
+        return (ch[0], ch[1]), (float(ms[0]), float(ms[1]))
+
     def growth_rate(self) -> float:
         g = C.c_double()
         self._ok(lib.pd_growth_rate(self._h, C.byref(g)))
         return g.value
+
+
+def variants(N: int, kind: int):
+    """Launch-shape variants of the row (kind 0) or column (kind 1) kernel."""
+    a, b = C.c_int(), C.c_int()
+    if lib.pd_variant_info(int(N), int(kind), -1, C.byref(a), C.byref(b)) != OK:
+        raise PitdynError(EINVAL, f"no variants for N={N}")
+    out = []
+    for v in range(a.value):
+        lib.pd_variant_info(int(N), int(kind), v, C.byref(a), C.byref(b))
+        out.append((a.value, b.value))
+    return out
+
+
+def select_variant(N: int, rows_v: int, cols_v: int):
+    st = lib.pd_select_variant(int(N), int(rows_v), int(cols_v))
+    if st != OK:
+        raise PitdynError(st, "invalid variant")
 
 
 class Batch:

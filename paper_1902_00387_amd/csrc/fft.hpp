@@ -39,13 +39,17 @@ __device__ __forceinline__ cplx mul_i(cplx a) {
 }
 __device__ __forceinline__ cplx czero() { return {0.0, 0.0}; }
 
-// LDS index padding: one extra slot every eight entries breaks the
-// 128-byte strides of the radix-8 scatter.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
+// LDS index padding: one extra 16-byte slot every 2^PAD_SHIFT entries spreads
+// the power-of-two strides of the Stockham scatter over the 64 LDS banks
+// (every 16 entries for N >= 64, every 8 below; chosen with a bank model of
+// the exchange patterns).
 template <int N>
 struct LdsSpan {
-  static constexpr int value = N + N / 8;
+  static constexpr int shift = N >= 64 ? 4 : 3;
+  static constexpr int value = N + (N >> shift);
 };
+template <int N>
+__device__ __forceinline__ int lpad(int i) { return i + (i >> LdsSpan<N>::shift); }
 
 // ---- small DFTs in registers ---------------------------------------------
 template <int DIR>
@@ -129,11 +133,11 @@ __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* __
     dftR<R, DIR>(x);
     const int base = (b / NS) * NS * R + jj;
 #pragma unroll
-    for (int k = 0; k < R; ++k) s[lpad(base + k * NS)] = x[k];
+    for (int k = 0; k < R; ++k) s[lpad<N>(base + k * NS)] = x[k];
   }
   group_sync();
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = s[lpad(j + T * e)];
+  for (int e = 0; e < E; ++e) v[e] = s[lpad<N>(j + T * e)];
   group_sync();
 }
 

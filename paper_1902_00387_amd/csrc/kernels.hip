@@ -155,16 +155,17 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 // (pitch TX + 1) so that global loads and stores run along x and all three
 // are in flight at once; once every group holds its column in registers the
 // tile memory doubles as the groups' FFT exchange spans.
-template <int N, int E>
+template <int N, int E, int LANES>
 __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restrict__ T1,
                                          cplx* __restrict__ T2, const cplx* __restrict__ tw,
                                          const FlowPhase& fp) {
   using G = Geo<N, E>;
   constexpr int T = G::T, K = G::K, M = G::M;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int TX = nthr / T < N ? nthr / T : N;
-  const int TP = TX + 1;
-  const int TS = M * TP;  // one component's tile
+  constexpr int nthr = LANES;
+  constexpr int TX = nthr / T < N ? nthr / T : N;
+  constexpr int TP = TX + 1;
+  constexpr int TS = M * TP;  // one component's tile
+  const int tid = threadIdx.x;
   const int g = tid / T, j = tid % T;
   const int x = x0 + g;
   const bool active = g < TX && x < N;
@@ -243,11 +244,10 @@ __host__ __device__ constexpr int tile_elems(int lanes) {
 
 // ---------------------------------------------------------------------------
 // Multi-launch path: one launch per phase over every (field, tile).
-template <int N>
-__global__ __launch_bounds__(64) void k_rows(FieldBatch fb, Problem pb, int mode, int last) {
-  constexpr int E = Shape<N>::ER;
+template <int N, int E, int W>
+__global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int mode, int last) {
   using G = Geo<N, E>;
-  constexpr int RPW = 64 / G::T;
+  constexpr int RPW = W * 64 / G::T;
   __shared__ cplx sm[RPW * G::SPAN];
   if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
   const int g = threadIdx.x / G::T, j = threadIdx.x % G::T;
@@ -261,18 +261,16 @@ __global__ __launch_bounds__(64) void k_rows(FieldBatch fb, Problem pb, int mode
                   fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, p, mode, last != 0);
 }
 
-template <int N>
-__global__ __launch_bounds__(Shape<N>::TXC * (N / Shape<N>::EC))
-__attribute__((amdgpu_waves_per_eu(N <= 256 ? 4 : 2))) void k_cols(FieldBatch fb, Problem pb,
-                                                                 int step) {
-  constexpr int E = Shape<N>::EC, TX = Shape<N>::TXC;
+template <int N, int E, int TX, int MINW>
+__global__ __launch_bounds__(TX * (N / E))
+__attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb, int step) {
   using G = Geo<N, E>;
   __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
   if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
   const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
   const size_t rows = (size_t)3 * G::M * N;
   const FlowPhase fp = flow_phase(pb, fb.t0[f] + step * pb.dt);
-  col_tile<N, E>(blockIdx.x * TX, tile, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
+  col_tile<N, E, TX * G::T>(blockIdx.x * TX, tile, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,7 +308,7 @@ __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* 
   __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
     const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
-    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC>(x0, tile, T1, T2, tw, fp);
+    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L>(x0, tile, T1, T2, tw, fp);
     const int mode = step == 0 ? 1 : 2;
     const bool last = step == nsteps - 1;
     for (int r0 = 0; r0 < M; r0 += NGR)
@@ -849,23 +847,176 @@ __global__ __launch_bounds__(256) void k_norm2(const cplx* __restrict__ x, size_
 
 // ---------------------------------------------------------------------------
 // Host launchers.
+template <int N, int E, int W>
+static hipError_t launch_rows_v(const FieldBatch& fb, const Problem& pb, int nfields, int mode,
+                                int last, hipStream_t st) {
+  using G = Geo<N, E>;
+  constexpr int RPW = W * 64 / G::T;
+  dim3 grid((G::M + RPW - 1) / RPW, nfields);
+  hipLaunchKernelGGL((k_rows<N, E, W>), grid, dim3(64 * W), 0, st, fb, pb, mode, last);
+  return hipGetLastError();
+}
+
+template <int N, int E, int TX, int MINW>
+static hipError_t launch_cols_v(const FieldBatch& fb, const Problem& pb, int nfields, int step,
+                                hipStream_t st) {
+  constexpr int T = N / E;
+  dim3 grid((N + TX - 1) / TX, nfields);
+  hipLaunchKernelGGL((k_cols<N, E, TX, MINW>), grid, dim3(TX * T), 0, st, fb, pb, step);
+  return hipGetLastError();
+}
+
+// ---- launch-shape variants and the per-size choice (autotuned) -----------
+using RowsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, int, hipStream_t);
+using ColsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, hipStream_t);
+struct RowsVariant {
+  int E, W;
+  RowsFn fn;
+};
+struct ColsVariant {
+  int E, TX;
+  ColsFn fn;
+};
+
+// Candidates: rows -- values a lane E (8 or 4), waves a workgroup W;
+// columns -- values a lane E, columns a workgroup TX (lanes <= 1024, LDS <= 160 KB).
+template <int N>
+struct Variants;
+template <>
+struct Variants<16> {
+  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<16, 8, 1>}};
+  static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<16, 4, 16, 4>}};
+};
+template <>
+struct Variants<32> {
+  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<32, 8, 1>}};
+  static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<32, 4, 16, 4>}};
+};
+template <>
+struct Variants<64> {
+  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<64, 8, 1>},
+                                         {8, 2, launch_rows_v<64, 8, 2>},
+                                         {4, 1, launch_rows_v<64, 4, 1>},
+                                         {4, 2, launch_rows_v<64, 4, 2>}};
+  static constexpr ColsVariant cols[] = {{4, 32, launch_cols_v<64, 4, 32, 4>},
+                                         {4, 16, launch_cols_v<64, 4, 16, 4>},
+                                         {8, 32, launch_cols_v<64, 8, 32, 2>},
+                                         {8, 16, launch_cols_v<64, 8, 16, 2>}};
+};
+template <>
+struct Variants<128> {
+  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<128, 8, 1>},
+                                         {8, 2, launch_rows_v<128, 8, 2>},
+                                         {4, 1, launch_rows_v<128, 4, 1>},
+                                         {4, 2, launch_rows_v<128, 4, 2>}};
+  static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<128, 4, 16, 4>},
+                                         {4, 8, launch_cols_v<128, 4, 8, 4>},
+                                         {8, 16, launch_cols_v<128, 8, 16, 2>},
+                                         {8, 32, launch_cols_v<128, 8, 32, 2>},
+                                         {8, 8, launch_cols_v<128, 8, 8, 2>}};
+};
+template <>
+struct Variants<256> {
+  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<256, 8, 1>},
+                                         {8, 2, launch_rows_v<256, 8, 2>},
+                                         {4, 1, launch_rows_v<256, 4, 1>}};
+  static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<256, 4, 16, 4>},
+                                         {4, 8, launch_cols_v<256, 4, 8, 4>},
+                                         {8, 16, launch_cols_v<256, 8, 16, 2>},
+                                         {8, 8, launch_cols_v<256, 8, 8, 2>}};
+};
+template <>
+struct Variants<512> {
+  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<512, 8, 1>},
+                                         {8, 2, launch_rows_v<512, 8, 2>}};
+  static constexpr ColsVariant cols[] = {{8, 8, launch_cols_v<512, 8, 8, 2>},
+                                         {8, 4, launch_cols_v<512, 8, 4, 2>}};
+};
+
+static int size_slot(int N) {
+  switch (N) {
+    case 16: return 0;
+    case 32: return 1;
+    case 64: return 2;
+    case 128: return 3;
+    case 256: return 4;
+    case 512: return 5;
+    default: return -1;
+  }
+}
+// chosen variant per size (process-wide; index 0 = default)
+static int g_rows_choice[6] = {0, 0, 0, 0, 0, 0};
+static int g_cols_choice[6] = {0, 0, 0, 0, 0, 0};
+
 template <int N>
 static hipError_t launch_rows(const FieldBatch& fb, const Problem& pb, int nfields, int mode,
                               int last, hipStream_t st) {
-  using G = Geo<N, Shape<N>::ER>;
-  constexpr int RPW = 64 / G::T;
-  dim3 grid((G::M + RPW - 1) / RPW, nfields);
-  hipLaunchKernelGGL(k_rows<N>, grid, dim3(64), 0, st, fb, pb, mode, last);
-  return hipGetLastError();
+  return Variants<N>::rows[g_rows_choice[size_slot(N)]].fn(fb, pb, nfields, mode, last, st);
 }
 
 template <int N>
 static hipError_t launch_cols(const FieldBatch& fb, const Problem& pb, int nfields, int step,
                               hipStream_t st) {
-  constexpr int TX = Shape<N>::TXC, T = N / Shape<N>::EC;
-  dim3 grid((N + TX - 1) / TX, nfields);
-  hipLaunchKernelGGL(k_cols<N>, grid, dim3(TX * T), 0, st, fb, pb, step);
-  return hipGetLastError();
+  return Variants<N>::cols[g_cols_choice[size_slot(N)]].fn(fb, pb, nfields, step, st);
+}
+
+template <int N>
+static int nvariants(int kind) {
+  return kind == 0 ? (int)(sizeof(Variants<N>::rows) / sizeof(RowsVariant))
+                   : (int)(sizeof(Variants<N>::cols) / sizeof(ColsVariant));
+}
+
+int variant_count(int N, int kind) {
+  switch (N) {
+    case 16: return nvariants<16>(kind);
+    case 32: return nvariants<32>(kind);
+    case 64: return nvariants<64>(kind);
+    case 128: return nvariants<128>(kind);
+    case 256: return nvariants<256>(kind);
+    case 512: return nvariants<512>(kind);
+    default: return 0;
+  }
+}
+
+template <int N>
+static void describe(int kind, int v, int* a, int* b) {
+  if (kind == 0) {
+    *a = Variants<N>::rows[v].E;
+    *b = Variants<N>::rows[v].W;
+  } else {
+    *a = Variants<N>::cols[v].E;
+    *b = Variants<N>::cols[v].TX;
+  }
+}
+
+int variant_describe(int N, int kind, int v, int* a, int* b) {
+  if (v < 0 || v >= variant_count(N, kind)) return -1;
+  switch (N) {
+    case 16: describe<16>(kind, v, a, b); break;
+    case 32: describe<32>(kind, v, a, b); break;
+    case 64: describe<64>(kind, v, a, b); break;
+    case 128: describe<128>(kind, v, a, b); break;
+    case 256: describe<256>(kind, v, a, b); break;
+    case 512: describe<512>(kind, v, a, b); break;
+    default: return -1;
+  }
+  return 0;
+}
+
+int variant_select(int N, int rows_v, int cols_v) {
+  const int sl = size_slot(N);
+  if (sl < 0 || rows_v < 0 || rows_v >= variant_count(N, 0) || cols_v < 0 ||
+      cols_v >= variant_count(N, 1))
+    return -1;
+  g_rows_choice[sl] = rows_v;
+  g_cols_choice[sl] = cols_v;
+  return 0;
+}
+
+void variant_current(int N, int* rows_v, int* cols_v) {
+  const int sl = size_slot(N);
+  *rows_v = sl < 0 ? 0 : g_rows_choice[sl];
+  *cols_v = sl < 0 ? 0 : g_cols_choice[sl];
 }
 
 template <int N>
@@ -884,6 +1035,54 @@ static hipError_t propagate_multi(const FieldBatch& fb, const Problem& pb, int n
     if (e == hipSuccess) e = launch_rows<N>(fb, pb, nfields, s == 0 ? 1 : 2, s == nsteps - 1, st);
   }
   return e;
+}
+
+// Two halves of the batch on two streams, the second started half a step
+// late, so that one half's column phase (transform-heavy) overlaps the
+// other half's row phase (memory-heavy).
+template <int N>
+static hipError_t propagate_multi2(const FieldBatch& fb, const Problem& pb, int nfields,
+                                   int nsteps, hipStream_t st, hipStream_t st2, hipEvent_t* ev) {
+  const int h = (nfields + 1) / 2;
+  FieldBatch fa = fb, fbb = fb;
+  const size_t box = (size_t)3 * Geo<N, 8>::M * Geo<N, 8>::M, rows = (size_t)3 * Geo<N, 8>::M * N;
+  fbb.B += h * box;
+  fbb.H += h * box;
+  fbb.T1 += h * rows;
+  fbb.T2 += h * rows;
+  fbb.t0 += h;
+  hipError_t e;
+  if ((e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(st2, ev[0], 0)) != hipSuccess) return e;
+  if ((e = launch_rows<N>(fa, pb, h, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_cols<N>(fa, pb, h, 0, st)) != hipSuccess) return e;
+  if ((e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(st2, ev[1], 0)) != hipSuccess) return e;
+  if ((e = launch_rows<N>(fbb, pb, nfields - h, 0, 0, st2)) != hipSuccess) return e;
+  for (int s = 0; s < nsteps; ++s) {
+    if (s > 0 && (e = launch_cols<N>(fa, pb, h, s, st)) != hipSuccess) return e;
+    if ((e = launch_rows<N>(fa, pb, h, s == 0 ? 1 : 2, s == nsteps - 1, st)) != hipSuccess) return e;
+    if ((e = launch_cols<N>(fbb, pb, nfields - h, s, st2)) != hipSuccess) return e;
+    if ((e = launch_rows<N>(fbb, pb, nfields - h, s == 0 ? 1 : 2, s == nsteps - 1, st2)) != hipSuccess)
+      return e;
+  }
+  if ((e = hipEventRecord(ev[2], st2)) != hipSuccess) return e;
+  return hipStreamWaitEvent(st, ev[2], 0);
+}
+
+hipError_t propagate2(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
+                      hipStream_t st, hipStream_t st2, hipEvent_t* ev) {
+  if (nfields <= 0 || nsteps <= 0) return hipSuccess;
+  if (nfields < 2) return propagate(N, fb, pb, nfields, nsteps, PATH_MULTI, st);
+  switch (N) {
+    case 16: return propagate_multi2<16>(fb, pb, nfields, nsteps, st, st2, ev);
+    case 32: return propagate_multi2<32>(fb, pb, nfields, nsteps, st, st2, ev);
+    case 64: return propagate_multi2<64>(fb, pb, nfields, nsteps, st, st2, ev);
+    case 128: return propagate_multi2<128>(fb, pb, nfields, nsteps, st, st2, ev);
+    case 256: return propagate_multi2<256>(fb, pb, nfields, nsteps, st, st2, ev);
+    case 512: return propagate_multi2<512>(fb, pb, nfields, nsteps, st, st2, ev);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,

@@ -69,7 +69,19 @@ hipError_t rows(int N, const FieldBatch& fb, const Problem& pb, int nfields, int
                 hipStream_t st);
 hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int step,
                 hipStream_t st);
+// the multi-launch path with the batch halved over two streams, the second
+// half started half a step later (ev: three events owned by the caller;
+// fields must not be remapped: fb.map and fb.count must be null)
+hipError_t propagate2(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
+                      hipStream_t st, hipStream_t st2, hipEvent_t* ev);
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
+// Launch-shape variants of the two phase kernels (kind 0: rows, 1: columns):
+// count, description (rows: values a lane, waves a workgroup; columns: values a
+// lane, columns a workgroup), process-wide selection and current choice.
+int variant_count(int N, int kind);
+int variant_describe(int N, int kind, int v, int* a, int* b);
+int variant_select(int N, int rows_v, int cols_v);
+void variant_current(int N, int* rows_v, int* cols_v);
 // same sweep with the explicit term as the exact spectral convolution with the
 // flow's four Fourier modes (N_C <= 64)
 hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);

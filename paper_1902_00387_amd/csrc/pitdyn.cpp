@@ -25,6 +25,8 @@ struct pd_ctx {
   int device = 0;
   hipStream_t own = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;      // second stream of the two-stream fine sweep
+  hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;
@@ -103,8 +105,18 @@ bool use_conv_sweep(const pd_ctx* c) {
 }
 
 int choose_path(const pd_ctx* c, int nfields) {
-  if (c->path == PD_PATH_MULTI || c->path == PD_PATH_SINGLE) return c->path;
+  if (c->path == PD_PATH_MULTI || c->path == PD_PATH_SINGLE || c->path == PD_PATH_MULTI2)
+    return c->path;
   return nfields >= 512 ? pd::PATH_SINGLE_WG : pd::PATH_MULTI;
+}
+
+// Fine propagation of a batch on the context's launch path.
+hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
+                      int nsteps, hipStream_t st) {
+  const int path = choose_path(c, nfields);
+  if (path == PD_PATH_MULTI2 && fb.map == nullptr)
+    return pd::propagate2(c->N, fb, pb, nfields, nsteps, st, c->side, c->sev);
+  return pd::propagate(c->N, fb, pb, nfields, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st);
 }
 
 // Validate `nfields` full-layout device fields: zero outside the 2/3 box.
@@ -165,7 +177,13 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
   fb.t0 = c->wt0.as<double>();
   fb.tw = twb->as<cplx>();
   const pd::Problem pb = make_problem(c, dt);
-  PD_HIP(c, pd::propagate(Ngrid, fb, pb, batch, nsteps, choose_path(c, batch), st), "propagate");
+  if (Ngrid == c->N) {
+    PD_HIP(c, fine_batch(c, fb, pb, batch, nsteps, st), "propagate");
+  } else {
+    const int path = choose_path(c, batch);
+    PD_HIP(c, pd::propagate(Ngrid, fb, pb, batch, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st),
+           "propagate");
+  }
   PD_HIP(c, pd::unpack(c->wB.as<cplx>(), static_cast<cplx*>(d_out), c->N, Mg, (size_t)batch, st),
          "unpack");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
@@ -185,7 +203,11 @@ pd_status pd_create(pd_ctx** out, int hip_device) {
   if (!c) return PD_ENOMEM;
   c->device = hip_device;
   DeviceGuard dg(hip_device);
-  if (hipStreamCreate(&c->own) != hipSuccess || hipHostMalloc((void**)&c->hred, 4 * sizeof(double)) != hipSuccess) {
+  if (hipStreamCreate(&c->own) != hipSuccess || hipStreamCreate(&c->side) != hipSuccess ||
+      hipEventCreateWithFlags(&c->sev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->sev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->sev[2], hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&c->hred, 4 * sizeof(double)) != hipSuccess) {
     delete c;
     return PD_EHIP;
   }
@@ -202,6 +224,12 @@ void pd_destroy(pd_ctx* c) {
       (void)hipStreamSynchronize(c->own);
       (void)hipStreamDestroy(c->own);
     }
+    if (c->side) {
+      (void)hipStreamSynchronize(c->side);
+      (void)hipStreamDestroy(c->side);
+    }
+    for (auto& e : c->sev)
+      if (e) (void)hipEventDestroy(e);
     if (c->hred) (void)hipHostFree(c->hred);
     c->tw.release(); c->twc.release(); c->U.release(); c->Fo.release(); c->Gold.release();
     c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
@@ -223,7 +251,7 @@ pd_status pd_set_stream(pd_ctx* c, void* s) {
 
 pd_status pd_set_path(pd_ctx* c, pd_path p) {
   if (!c) return PD_EINVAL;
-  if (p != PD_PATH_AUTO && p != PD_PATH_MULTI && p != PD_PATH_SINGLE)
+  if (p != PD_PATH_AUTO && p != PD_PATH_MULTI && p != PD_PATH_SINGLE && p != PD_PATH_MULTI2)
     return fail(c, PD_EINVAL, "unknown path %d", (int)p);
   c->path = p;
   return PD_OK;
@@ -459,7 +487,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
     fb.t0 = c->t0s.as<double>() + n0;
     fb.tw = c->tw.as<cplx>();
-    PD_HIP(c, pd::propagate(c->N, fb, pf, P - n0, c->nf, choose_path(c, P - n0), st), "fine sweep");
+    PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
     PD_HIP(c, hipEventRecord(ev[1], st), "event");
     // serial coarse sweep with the correction, then the defect sums
     sa.n0 = n0;
@@ -523,13 +551,13 @@ pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
   // a whole fine sweep (all slices, every step) as Parareal launches it
   PD_HIP(c, fresh(), "copy");
   PD_HIP(c, hipEventRecord(ev[0], st), "event");
-  PD_HIP(c, pd::propagate(c->N, fb, pf, P, c->nf, choose_path(c, P), st), "propagate");
+  PD_HIP(c, fine_batch(c, fb, pf, P, c->nf, st), "propagate");
   PD_HIP(c, hipEventRecord(ev[1], st), "event");
   PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
   PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
   ms[2] = t / c->nf;
   ms[0] = ms[1] = 0.0;
-  if (choose_path(c, P) == pd::PATH_MULTI) {
+  if (choose_path(c, P) != pd::PATH_SINGLE_WG) {
     // each phase kernel back to back, reps times, over the same batch
     PD_HIP(c, fresh(), "copy");
     PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
@@ -546,6 +574,155 @@ pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
     PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
     ms[1] = t / reps;
   }
+  return PD_OK;
+}
+
+// ---- autotuner --------------------------------------------------------------
+namespace {
+
+std::string tune_key(int device, int N, int P) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  return arch + "|" + std::to_string(N) + "|" + std::to_string(P);
+}
+
+// The cache is a flat JSON object {"<arch>|<N>|<batch>": [rows, cols], ...}.
+bool cache_lookup(const char* path, const std::string& key, int* rv, int* cv) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  const std::string q = "\"" + key + "\"";
+  const size_t at = text.find(q);
+  if (at == std::string::npos) return false;
+  return std::sscanf(text.c_str() + at + q.size(), " : [ %d , %d ]", rv, cv) == 2;
+}
+
+void cache_store(const char* path, const std::string& key, int rv, int cv) {
+  std::vector<std::pair<std::string, std::pair<int, int>>> entries;
+  FILE* f = std::fopen(path, "r");
+  if (f) {
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    size_t pos = 0;
+    while ((pos = text.find('"', pos)) != std::string::npos) {
+      const size_t end = text.find('"', pos + 1);
+      if (end == std::string::npos) break;
+      const std::string k = text.substr(pos + 1, end - pos - 1);
+      int a = 0, b = 0;
+      if (std::sscanf(text.c_str() + end + 1, " : [ %d , %d ]", &a, &b) == 2 && k != key)
+        entries.push_back({k, {a, b}});
+      pos = end + 1;
+    }
+  }
+  entries.push_back({key, {rv, cv}});
+  f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i)
+    std::fprintf(f, "  \"%s\": [%d, %d]%s\n", entries[i].first.c_str(), entries[i].second.first,
+                 entries[i].second.second, i + 1 < entries.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+}
+
+}  // namespace
+
+pd_status pd_variant_info(int N, int kind, int v, int* a, int* b) {
+  if (!a || !b || (kind != 0 && kind != 1)) return PD_EINVAL;
+  if (v == -1) {
+    *a = pd::variant_count(N, kind);
+    *b = 0;
+    return *a > 0 ? PD_OK : PD_EINVAL;
+  }
+  return pd::variant_describe(N, kind, v, a, b) == 0 ? PD_OK : PD_EINVAL;
+}
+
+pd_status pd_select_variant(int N, int rows_v, int cols_v) {
+  return pd::variant_select(N, rows_v, cols_v) == 0 ? PD_OK : PD_EINVAL;
+}
+
+pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, double* ms) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (reps < 1) return fail(c, PD_EINVAL, "reps must be >= 1");
+  DeviceGuard dg(c->device);
+  const std::string key = tune_key(c->device, c->N, c->P);
+  int rv = 0, cv = 0;
+  if (cache_path && cache_lookup(cache_path, key, &rv, &cv) &&
+      pd::variant_select(c->N, rv, cv) == 0) {
+    if (chosen) {
+      chosen[0] = rv;
+      chosen[1] = cv;
+    }
+    if (ms) ms[0] = ms[1] = 0.0;
+    return PD_OK;
+  }
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems();
+  const int P = c->P;
+  hipEvent_t ev[2];
+  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evf{ev};
+  pd::FieldBatch fb;
+  fb.B = c->Fo.as<cplx>();
+  fb.H = c->Hf.as<cplx>();
+  fb.T1 = c->T1f.as<cplx>();
+  fb.T2 = c->T2f.as<cplx>();
+  fb.t0 = c->t0s.as<double>();
+  fb.tw = c->tw.as<cplx>();
+  const pd::Problem pf = make_problem(c, c->dtf);
+  int cur_r = 0, cur_c = 0;
+  pd::variant_current(c->N, &cur_r, &cur_c);
+  auto timed = [&](int kind, float* out) -> hipError_t {
+    hipError_t e = hipEventRecord(ev[0], st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+      e = kind == 0 ? pd::rows(c->N, fb, pf, P, 2, 0, st) : pd::cols(c->N, fb, pf, P, 1, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(out, ev[0], ev[1]);
+    return e;
+  };
+  PD_HIP(c, hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx), hipMemcpyDeviceToDevice, st), "copy");
+  PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
+  float best[2] = {1e30f, 1e30f};
+  int bestv[2] = {cur_r, cur_c};
+  for (int kind = 0; kind < 2; ++kind) {
+    const int nv = pd::variant_count(c->N, kind);
+    for (int v = 0; v < nv; ++v) {
+      pd::variant_select(c->N, kind == 0 ? v : bestv[0], kind == 1 ? v : cur_c);
+      float t = 0;
+      PD_HIP(c, timed(kind, &t), "autotune");  // warm-up
+      PD_HIP(c, timed(kind, &t), "autotune");
+      if (t < best[kind]) {
+        best[kind] = t;
+        bestv[kind] = v;
+      }
+    }
+  }
+  pd::variant_select(c->N, bestv[0], bestv[1]);
+  if (chosen) {
+    chosen[0] = bestv[0];
+    chosen[1] = bestv[1];
+  }
+  if (ms) {
+    ms[0] = best[0] / reps;
+    ms[1] = best[1] / reps;
+  }
+  if (cache_path) cache_store(cache_path, key, bestv[0], bestv[1]);
   return PD_OK;
 }
 

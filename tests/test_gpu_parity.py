@@ -44,7 +44,7 @@ def ctx(lib):
     c.close()
 
 
-@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("path", [0, 1, 2])
 @pytest.mark.parametrize("flow", ["roberts", "gp"])
 @pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512])
 def test_steps_match_oracle(ctx, lib, N, flow, path):
@@ -101,7 +101,7 @@ def test_batch_invariance_and_determinism(ctx):
     x = rand_box(N, 5, 4)
     t0 = np.array([0.3, 0.3, 0.3, 0.3])
     outs = []
-    for path in (0, 1):
+    for path in (0, 1, 2):
         ctx.set_path(path)
         a = ctx.steps(t0, 1e-2, 5, dev(x)).cpu().numpy()
         b = ctx.steps(t0, 1e-2, 5, dev(x)).cpu().numpy()
@@ -110,6 +110,7 @@ def test_batch_invariance_and_determinism(ctx):
         assert np.array_equal(a[2], c[0])
         outs.append(a)
     assert rel(outs[0], outs[1]) <= TOL
+    assert np.array_equal(outs[0], outs[2])
 
 
 def test_config1_parareal_matches_oracle(ctx):
@@ -230,3 +231,54 @@ def test_parareal_coarse_forms_match_oracle(ctx, lib, form):
     for n in range(P + 1):
         assert rel(U[n], ref.U[n]) <= TOL, (form, n, rel(U[n], ref.U[n]))
     assert np.allclose(rep["sigma"], ref.sigma, rtol=0, atol=2 * TOL)
+
+
+@pytest.mark.parametrize("N", [64, 128, 256, 512])
+def test_every_launch_variant_matches_oracle(ctx, lib, N):
+    """Each launch-shape variant of the row and column kernels reproduces the
+    oracle (the autotuner may pick any of them)."""
+    kz, Rm, dt, nsteps = 0.57, 40.0, 2e-3, 2
+    x = rand_box(N, 11 + N, 2)
+    t0 = np.array([0.4, 3.3])
+    refs = [stepper.propagate(x[f], "gp", Rm, kz, t0[f], dt, nsteps) for f in range(2)]
+    ctx.set_problem("gp", Rm, kz, N)
+    ctx.set_path(0)
+    try:
+        for kind in (0, 1):
+            for v in range(len(lib.variants(N, kind))):
+                lib.select_variant(N, v if kind == 0 else 0, v if kind == 1 else 0)
+                print(f"variant N={N} kind={kind} v={v}", flush=True)
+                y = ctx.steps(t0, dt, nsteps, dev(x)).cpu().numpy()
+                for f in range(2):
+                    assert rel(y[f], refs[f]) <= TOL, (kind, v, f)
+    finally:
+        lib.select_variant(N, 0, 0)
+
+
+def test_autotune_selects_and_caches(ctx, lib, tmp_path):
+    N = 64
+    ctx.set_problem("gp", 50.0, 0.57, N)
+    ctx.set_time(4.0, 8, 1e-2, 5e-2, 32)
+    ctx.set_initial(initial_field(N, 0.57, 5))
+    ctx.parareal(0.0, 0)
+    cache = str(tmp_path / "tune.json")
+    try:
+        (rv, cv), (mr, mc) = ctx.autotune(5, cache)
+        assert 0 <= rv < len(lib.variants(N, 0)) and 0 <= cv < len(lib.variants(N, 1))
+        assert mr > 0 and mc > 0
+        text = open(cache).read()
+        assert f"|{N}|8" in text
+        (rv2, cv2), (mr2, mc2) = ctx.autotune(5, cache)   # cache hit
+        assert (rv2, cv2) == (rv, cv) and mr2 == 0.0
+        # Parareal after tuning still matches the untuned run to the parity bar
+        ctx.set_initial(initial_field(N, 0.57, 5))
+        ctx.parareal(0.0, 2)
+        U1 = ctx.get_slices()
+        lib.select_variant(N, 0, 0)
+        ctx.set_initial(initial_field(N, 0.57, 5))
+        ctx.parareal(0.0, 2)
+        U0 = ctx.get_slices()
+        for n in range(9):
+            assert rel(U1[n], U0[n]) <= TOL
+    finally:
+        lib.select_variant(N, 0, 0)
