@@ -71,6 +71,61 @@ def cpu_baseline(budget_s=15.0):
                       f"(serial, {dt:.1f} s)"}
 
 
+KERNELS_SRC = os.path.join(ROOT, "paper_1902_00387_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gp128_p64.json")
+
+
+def kernels_digest():
+    import hashlib
+    with open(KERNELS_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def summarize_pmc(fetch_csv, write_csv, out_path):
+    """Per-dispatch HBM traffic of the fine step's kernels from two rocprofv3
+    --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by the same
+    counters on a plain 1 GiB device copy."""
+    import csv
+    import statistics
+
+    def per_kernel(path):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy_bytes = float(1 << 30)
+    cf = max(v for k, vs in fetch.items() if "copyBuffer" in k for v in vs) * 1024.0
+    cw = max(v for k, vs in write.items() if "copyBuffer" in k for v in vs) * 1024.0
+    out = {"kernels_sha256_16": kernels_digest(), "fetch_scale": copy_bytes / cf,
+           "write_scale": copy_bytes / cw, "kernels": {}}
+    for name in fetch:
+        if "k_rows" not in name and "k_cols" not in name:
+            continue
+        f = statistics.median(fetch[name]) * 1024.0 * out["fetch_scale"]
+        w = statistics.median(write.get(name, [0.0])) * 1024.0 * out["write_scale"]
+        out["kernels"][name] = {"fetch_bytes": f, "write_bytes": w, "dispatches": len(fetch[name])}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch of the kernel from the committed counter summary,
+    or None if the summary is missing or the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernels_sha256_16") != kernels_digest():
+        return None
+    for name, v in d["kernels"].items():
+        if name.split("(")[0].replace(" ", "").endswith(kernel_prefix.replace(" ", "")):
+            return v["fetch_bytes"] + v["write_bytes"]
+    return None
+
+
 def batch_workload(scale=1.0):
     """Many independent Galloway-Proctor problems of uneven size: 96 at 64^2,
     96 at 128^2 and 64 at 256^2 (times `scale`), Rm log-uniform in [10, 1000],
@@ -154,7 +209,12 @@ def main():
                     help="the many-instance workload instead of the single solve")
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary from two rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_FILE)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
               "path here is single-GPU; see DESIGN.md for how it would shard.", file=sys.stderr)
@@ -227,6 +287,8 @@ def main():
     cols_b, rows_b = kernel_bytes(N, P)
     dominant = ("cols", ms_cols, cols_b) if ms_cols >= ms_rows else ("rows", ms_rows, rows_b)
     achieved = dominant[2] / (dominant[1] * 1e-3) / 1e9
+    dom_name = ("k_cols<128,%d,%d>" % tuple(pd.variants(N, 1)[tuned[1]]) if dominant[0] == "cols"
+                else "k_rows<128,%d,%d>" % tuple(pd.variants(N, 0)[tuned[0]]))
     fine_rate = N * N * P / (ms_fstep * 1e-3)
     alg_per_mode = (cols_b + rows_b) / (N * N * P)
 
@@ -279,13 +341,15 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cols<128,%d,%d>" % tuple(pd.variants(N, 1)[tuned[1]]) if dominant[0] == "cols"
-                      else "k_rows<128,%d,%d>" % tuple(pd.variants(N, 0)[tuned[0]]),
+            "kernel": dom_name,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("pd::" + dom_name),
+            "traffic_note": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the same "
+                            "counters on a 1 GiB copy) from profiles/traffic_gp128_p64.json; null "
+                            "if the kernels changed since the counters were taken",
         },
     }
     if not args.no_cpu_baseline:
