@@ -193,6 +193,59 @@ pd_status pd_slice_norms(const pd_ctx* ctx, double* norms);
    growth rates without naming an estimator; this is the reading used). */
 pd_status pd_growth_rate(const pd_ctx* ctx, double* gamma);
 
+/* ---- Learned coarse propagator --------------------------------------------
+ * The Parareal coarse propagator G (Section 3) may be replaced by
+ *   G_learned(D) = G(D) + |D| Net(D/|D|, G(D)/|D|; t_n),
+ * G the plain coarse step of this context and Net a small linear spectral
+ * neural operator on the fine 2/3 box (lift of the 12 real inputs a mode to
+ * 32 channels; `layers` residual layers mixing channels over the mode and its
+ * four neighbours with weights V_{l,0,s} + cos t_n V_{l,1,s} + sin t_n V_{l,2,s}
+ * and per-mode channel gains; projection to 3 complex values a mode).  It is
+ * trained on pairs (D, F(D) - G(D)) that the library's own fine and coarse
+ * propagators generate, with BF16 matrix-core (MFMA, FP32 accumulate)
+ * forward and backward kernels and Adam on FP32 master weights.  Parareal
+ * then runs in difference form U^k_{n+1} = F(U^{k-1}_n) + G_learned(U^k_n -
+ * U^{k-1}_n), the same iteration for a linear coarse propagator; G_learned(0)
+ * = 0, so converged slices stay bitwise equal to F.  The state belongs to the
+ * context and is dropped by pd_set_problem / pd_set_time. */
+
+/* Create the network (layers in [1, 8]) with seeded initial weights. */
+pd_status pd_lg_init(pd_ctx* ctx, int layers, uint64_t seed);
+/* Add n training samples: device fields D (full layout [n][3][N][N]) and
+   slice start times t0 (host); the library computes F(D) and G(D). */
+pd_status pd_lg_add_samples(pd_ctx* ctx, int n, const double* t0, const void* d_D,
+                            void* hip_stream);
+/* Add the fields the coarse propagator sees in a plain-G Parareal run from
+   the context's initial field: U^0_n (n < P) of the initial coarse run and
+   U^k_n - U^{k-1}_n (k <= n < P) after each of `iters` iterations, each with
+   its slice start time; *n_stored (may be null) receives the number of
+   stored samples afterwards, the new ones last.  Leaves the context's slice
+   states at that run's last iterate (set the initial field again before
+   pd_parareal).  iters must be in [0, n_slices). */
+pd_status pd_lg_add_parareal_samples(pd_ctx* ctx, int iters, int* n_stored);
+/* `steps` Adam steps (learning rate lr) on batches of `batch` distinct
+   samples from the stored range [first, first + count), drawn with a seeded
+   splitmix64 stream; loss = sum |c - r|^2 / sum |r|^2 with
+   r = (F(D) - G(D))/|D|; losses[steps] (may be NULL) receives each step's
+   batch loss. */
+pd_status pd_lg_train(pd_ctx* ctx, int first, int count, int steps, int batch, double lr,
+                      uint64_t seed, double* losses);
+/* Loss over stored samples [first, first + count). */
+pd_status pd_lg_loss(pd_ctx* ctx, int first, int count, double* loss);
+/* Gradient of the loss over samples [first, first + count) with respect to
+   the flat parameter vector (float[n] as pd_lg_params), and the loss. */
+pd_status pd_lg_gradients(pd_ctx* ctx, int first, int count, float* grads, double* loss);
+/* Flat FP32 parameters W_in[12][32] | V[L][3][5][32][32] | gamma[L][Q][32] |
+   W_out[32][6] (Q = (2K+1)^2): with out NULL *n receives the count. */
+pd_status pd_lg_params(pd_ctx* ctx, float* out, size_t* n);
+pd_status pd_lg_set_params(pd_ctx* ctx, const float* in, size_t n);
+/* Stored sample i: features x[Q][12], targets r[Q][6], slice time t. */
+pd_status pd_lg_sample(pd_ctx* ctx, int i, float* x, float* r, double* t);
+/* Network output c[Q][6] on stored sample i. */
+pd_status pd_lg_forward_sample(pd_ctx* ctx, int i, float* out);
+/* Use the learned (1) or plain (0) coarse propagator in pd_parareal. */
+pd_status pd_set_coarse(pd_ctx* ctx, int learned);
+
 /* ---- Many independent problems in one batch -------------------------------
  * Parareal (Section 3) for many (flow, Rm, kz, N) instances of uneven size at
  * once on one GPU.  Instances of equal (flow, N, fine steps per slice) share

@@ -11,9 +11,10 @@ Modules
   spectral  grid, wavenumbers, 2/3 box, flows, explicit operator curl(u x b)
   stepper   IMEX SBDF1/SBDF2 slice propagators, Fourier restriction/prolongation
   parareal  Parareal iteration, defect, growth rate, speed-up model
+  network   FP64 reference of the learned coarse-propagator correction
 
 Parity status of each function is stated in its docstring; every function is
 pinned by a CPU test in ``tests/test_oracle_*.py`` except where the docstring
 says "parity unpinned".
 """
-from . import spectral, stepper, parareal  # noqa: F401
+from . import spectral, stepper, parareal, network  # noqa: F401

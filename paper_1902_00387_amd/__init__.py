@@ -40,6 +40,8 @@ SYMBOLS = [
     "pd_batch_create", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_add",
     "pd_batch_run", "pd_batch_result", "pd_batch_get_slices", "pd_batch_time",
     "pd_autotune", "pd_variant_info", "pd_select_variant",
+    "pd_lg_init", "pd_lg_add_samples", "pd_lg_add_parareal_samples", "pd_lg_train", "pd_lg_loss", "pd_lg_gradients",
+    "pd_lg_params", "pd_lg_set_params", "pd_lg_sample", "pd_lg_forward_sample", "pd_set_coarse",
 ]
 
 
@@ -108,6 +110,17 @@ def _load():
         "pd_autotune": ([vp, i, C.c_char_p, C.POINTER(i), dp], i),
         "pd_variant_info": ([i, i, i, C.POINTER(i), C.POINTER(i)], i),
         "pd_select_variant": ([i, i, i], i),
+        "pd_lg_init": ([vp, i, C.c_uint64], i),
+        "pd_lg_add_samples": ([vp, i, dp, vp, vp], i),
+        "pd_lg_add_parareal_samples": ([vp, i, vp], i),
+        "pd_lg_train": ([vp, i, i, i, i, d, C.c_uint64, dp], i),
+        "pd_lg_loss": ([vp, i, i, dp], i),
+        "pd_lg_gradients": ([vp, i, i, C.POINTER(C.c_float), dp], i),
+        "pd_lg_params": ([vp, C.POINTER(C.c_float), C.POINTER(C.c_size_t)], i),
+        "pd_lg_set_params": ([vp, C.POINTER(C.c_float), C.c_size_t], i),
+        "pd_lg_sample": ([vp, i, C.POINTER(C.c_float), C.POINTER(C.c_float), dp], i),
+        "pd_lg_forward_sample": ([vp, i, C.POINTER(C.c_float)], i),
+        "pd_set_coarse": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +280,74 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         self._ok(lib.pd_autotune(self._h, int(reps), cp, ch, _dptr(ms)))
         return (ch[0], ch[1]), (float(ms[0]), float(ms[1]))
+
+    # -- learned coarse propagator -------------------------------------------
+    def lg_init(self, layers: int = 4, seed: int = 0):
+        self._ok(lib.pd_lg_init(self._h, int(layers), C.c_uint64(seed)))
+
+    def lg_add_samples(self, t0, D):
+        _check_dev(D, self.N)
+        Db = D.reshape(-1, 3, self.N, self.N)
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, np.float64), (Db.shape[0],)))
+        self._ok(lib.pd_lg_add_samples(self._h, Db.shape[0], _dptr(t), C.c_void_p(Db.data_ptr()),
+                                       _stream()))
+
+    def lg_add_parareal_samples(self, iters: int) -> int:
+        """Store the coarse-propagator inputs of a plain-G Parareal run from
+        the current initial field (iterations 0..iters); returns the number
+        of stored samples."""
+        n = C.c_int(0)
+        self._ok(lib.pd_lg_add_parareal_samples(self._h, int(iters), C.byref(n)))
+        return n.value
+
+    def lg_train(self, first: int, count: int, steps: int, batch: int, lr: float,
+                 seed: int = 0) -> np.ndarray:
+        losses = np.zeros(max(steps, 1), np.float64)
+        self._ok(lib.pd_lg_train(self._h, int(first), int(count), int(steps), int(batch),
+                                 float(lr), C.c_uint64(seed), _dptr(losses)))
+        return losses[:steps]
+
+    def lg_loss(self, first: int, count: int) -> float:
+        v = C.c_double()
+        self._ok(lib.pd_lg_loss(self._h, int(first), int(count), C.byref(v)))
+        return v.value
+
+    def lg_params(self) -> np.ndarray:
+        n = C.c_size_t(0)
+        self._ok(lib.pd_lg_params(self._h, None, C.byref(n)))
+        out = np.zeros(n.value, np.float32)
+        self._ok(lib.pd_lg_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
+        return out
+
+    def lg_set_params(self, p):
+        a = np.ascontiguousarray(np.asarray(p, np.float32))
+        self._ok(lib.pd_lg_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def lg_gradients(self, first: int, count: int):
+        g = np.zeros(self.lg_params().size, np.float32)
+        v = C.c_double()
+        self._ok(lib.pd_lg_gradients(self._h, int(first), int(count),
+                                     g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(v)))
+        return g, v.value
+
+    def lg_sample(self, i: int):
+        M = 2 * ((self.N - 1) // 3) + 1
+        Q = M * M
+        x = np.zeros((Q, 12), np.float32)
+        r = np.zeros((Q, 6), np.float32)
+        t = C.c_double()
+        self._ok(lib.pd_lg_sample(self._h, int(i), x.ctypes.data_as(C.POINTER(C.c_float)),
+                                  r.ctypes.data_as(C.POINTER(C.c_float)), C.byref(t)))
+        return x, r, t.value
+
+    def lg_forward_sample(self, i: int) -> np.ndarray:
+        M = 2 * ((self.N - 1) // 3) + 1
+        out = np.zeros((M * M, 6), np.float32)
+        self._ok(lib.pd_lg_forward_sample(self._h, int(i), out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_coarse(self, learned: bool):
+        self._ok(lib.pd_set_coarse(self._h, int(bool(learned))))
 
     def growth_rate(self) -> float:
         g = C.c_double()

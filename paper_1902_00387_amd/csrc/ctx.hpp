@@ -1,0 +1,96 @@
+// The context of the C ABI (pd_ctx) and the helpers shared by the runtime
+// files that implement its calls.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/pitdyn.h"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+using pd::rt::DevBuf;
+using pd::cplx;
+
+struct pd_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;      // second stream of the two-stream fine sweep
+  hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
+  std::string err;
+  int path = PD_PATH_AUTO;
+  int coarse_form = PD_COARSE_AUTO;
+  // problem
+  bool have_problem = false;
+  int flow = PD_FLOW_NONE;
+  double Rm = 1, kz = 0;
+  int N = 0, K = 0, M = 0;
+  // time grid
+  bool have_time = false;
+  double T = 0, dT = 0, dtf = 0, dtc = 0;
+  int P = 0, Nc = 0, Mc = 0, nf = 0, nc = 0;
+  bool have_initial = false;
+  // device memory
+  DevBuf tw, twc;                      // twiddles (fine, coarse)
+  DevBuf U, Fo, Gold, Hf, T1f, T2f;    // slice buffers
+  DevBuf Uprev, t0s;                   // defect copy, slice start times
+  DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
+  DevBuf red, flag;                    // reduction outputs, box-check flag
+  DevBuf ftab;                         // flow phases at every coarse step time
+  DevBuf wB, wH, wT1, wT2, wt0;        // workspaces of the propagator calls
+  double* hred = nullptr;              // pinned host copy of red
+  // learned coarse propagator (correction network) state
+  struct LG {
+    bool init = false, enabled = false;
+    int L = 0, Q = 0, Mf = 0, step = 0;
+    DevBuf params, grads, m1, m2;      // FP32 vectors of nn::param_count values
+    int S = 0;                         // stored samples
+    DevBuf xs, rs, ts;                 // [S][Q][12] features, [S][Q][6] targets, [S] slice times
+    int Bcap = 0;                      // batch capacity of the activation buffers
+    DevBuf act, ys, c, dc, dhA, dhB, dW, part, lpart, sums, bidx;
+    int* hbidx = nullptr;              // pinned batch indices
+    DevBuf Dn, gn, fn, nrm, uold;      // sweep and sample work (compact fine box)
+  } lg;
+
+  size_t box_elems() const { return (size_t)3 * M * M; }
+  size_t rows_elems() const { return (size_t)3 * M * N; }
+};
+
+namespace pd {
+namespace ctxh {
+
+pd_status fail(pd_ctx* c, pd_status s, const char* fmt, ...);
+pd_status hipfail(pd_ctx* c, hipError_t e, const char* what);
+
+#define PD_HIP(ctx, expr, what)                            \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hipfail(ctx, e_, what);   \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(d);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+pd::Problem make_problem(const pd_ctx* c, double dt);
+bool use_conv_sweep(const pd_ctx* c);
+int choose_path(const pd_ctx* c, int nfields);
+hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
+                      int nsteps, hipStream_t st);
+pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStream_t st);
+pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
+                         int Ngrid, const void* d_in, void* d_out, hipStream_t st);
+// learned coarse propagator (lg.cpp)
+void lg_release(pd_ctx* c);
+pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st);
+
+}  // namespace ctxh
+}  // namespace pd

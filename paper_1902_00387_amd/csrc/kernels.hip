@@ -358,7 +358,7 @@ __global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem
       a.Bc[i] = Un[(c * M + rr + K - Kc) * M + cc + K - Kc];
     }
     __syncthreads();
-    propagate_wg<NC>(lds, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, n * a.dT, a.nsteps);
+    propagate_wg<NC>(lds, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, (a.nbase + n) * a.dT, a.nsteps);
     cplx* Un1 = a.U + (n + 1) * fbox;
     cplx* Go = a.Gold + n * fbox;
     const cplx* Fn = a.Fo + n * fbox;
@@ -473,11 +473,11 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
         if (own[m] < nbox) bs[c * nbox + own[m]] = Un[(c * M + oky[m] + K) * M + okx[m] + K];
       }
     __syncthreads();
-    const double t0 = n * a.dT;
+    const double t0 = (a.nbase + n) * a.dT;
     for (int step = 0; step < a.nsteps; ++step) {
       FlowModes fm;
       if (a.ftab != nullptr && pb.tdep) {
-        const double* ft = a.ftab + 4 * ((size_t)n * a.nsteps + step);
+        const double* ft = a.ftab + 4 * ((size_t)(a.nbase + n) * a.nsteps + step);
         const double h = 0.5 * pb.amp;
         fm.ap = {h * ft[0], h * ft[1]};
         fm.am = {h * ft[0], -h * ft[1]};
@@ -655,11 +655,11 @@ __device__ __forceinline__ void sweep_conv_global(const SweepArgs& a, const Prob
       buf[0][i] = Un[(c * M + ky + K) * M + kx + K];
     }
     __syncthreads();
-    const double t0 = n * a.dT;
+    const double t0 = (a.nbase + n) * a.dT;
     for (int step = 0; step < a.nsteps; ++step) {
       FlowModes fm;
       if (a.ftab != nullptr && pb.tdep) {
-        const double* ft = a.ftab + 4 * ((size_t)n * a.nsteps + step);
+        const double* ft = a.ftab + 4 * ((size_t)(a.nbase + n) * a.nsteps + step);
         const double h = 0.5 * pb.amp;
         fm.ap = {h * ft[0], h * ft[1]};
         fm.am = {h * ft[0], -h * ft[1]};

@@ -53,6 +53,7 @@ struct SweepArgs {
   int P, n0;          // slices, first slice swept
   int nsteps;         // coarse steps per slice
   int mode;           // 0: initial coarse run, 1: correction
+  int nbase = 0;      // absolute index of local slice 0 (start time (nbase + n) dT)
 };
 
 struct SweepJob {

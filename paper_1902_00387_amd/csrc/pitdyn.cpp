@@ -16,45 +16,15 @@
 #include "../../include/pitdyn.h"
 #include "launch.hpp"
 #include "runtime.hpp"
+#include "ctx.hpp"
 
 using pd::cplx;
 
 using namespace pd::rt;
 
-struct pd_ctx {
-  int device = 0;
-  hipStream_t own = nullptr;
-  hipStream_t stream = nullptr;
-  hipStream_t side = nullptr;      // second stream of the two-stream fine sweep
-  hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
-  std::string err;
-  int path = PD_PATH_AUTO;
-  int coarse_form = PD_COARSE_AUTO;
-  // problem
-  bool have_problem = false;
-  int flow = PD_FLOW_NONE;
-  double Rm = 1, kz = 0;
-  int N = 0, K = 0, M = 0;
-  // time grid
-  bool have_time = false;
-  double T = 0, dT = 0, dtf = 0, dtc = 0;
-  int P = 0, Nc = 0, Mc = 0, nf = 0, nc = 0;
-  bool have_initial = false;
-  // device memory
-  DevBuf tw, twc;                      // twiddles (fine, coarse)
-  DevBuf U, Fo, Gold, Hf, T1f, T2f;    // slice buffers
-  DevBuf Uprev, t0s;                   // defect copy, slice start times
-  DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
-  DevBuf red, flag;                    // reduction outputs, box-check flag
-  DevBuf ftab;                         // flow phases at every coarse step time
-  DevBuf wB, wH, wT1, wT2, wt0;        // workspaces of the propagator calls
-  double* hred = nullptr;              // pinned host copy of red
 
-  size_t box_elems() const { return (size_t)3 * M * M; }
-  size_t rows_elems() const { return (size_t)3 * M * N; }
-};
-
-namespace {
+namespace pd {
+namespace ctxh {
 
 pd_status fail(pd_ctx* c, pd_status s, const char* fmt, ...) {
   char buf[512];
@@ -71,23 +41,6 @@ pd_status hipfail(pd_ctx* c, hipError_t e, const char* what) {
     return fail(c, PD_ENOMEM, "%s: out of device memory", what);
   return fail(c, PD_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define PD_HIP(ctx, expr, what)                       \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
-    if (e_ != hipSuccess) return hipfail(ctx, e_, what); \
-  } while (0)
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int d) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    (void)hipSetDevice(d);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 pd::Problem make_problem(const pd_ctx* c, double dt) {
   pd::Problem pb;
@@ -190,7 +143,10 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
   return PD_OK;
 }
 
-}  // namespace
+}  // namespace ctxh
+}  // namespace pd
+
+using namespace pd::ctxh;
 
 extern "C" {
 
@@ -231,6 +187,7 @@ void pd_destroy(pd_ctx* c) {
     for (auto& e : c->sev)
       if (e) (void)hipEventDestroy(e);
     if (c->hred) (void)hipHostFree(c->hred);
+    lg_release(c);
     c->tw.release(); c->twc.release(); c->U.release(); c->Fo.release(); c->Gold.release();
     c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
     c->Bc.release(); c->Hc.release(); c->T1c.release(); c->T2c.release(); c->red.release();
@@ -277,6 +234,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   if (!valid_N(N)) return fail(c, PD_EINVAL, "N must be one of 16, 32, 64, 128, 256, 512");
   DeviceGuard dg(c->device);
   c->have_problem = c->have_time = c->have_initial = false;
+  lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
   c->T2f.release(); c->Uprev.release();
   c->flow = flow;
@@ -306,6 +264,7 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   if (!integer_ratio(dT, dtc, &nc)) return fail(c, PD_EINVAL, "slice length is not an integer number of coarse steps");
   DeviceGuard dg(c->device);
   c->have_time = c->have_initial = false;
+  lg_release(c);
   c->T = T; c->P = P; c->dT = dT; c->dtf = dtf; c->dtc = dtc; c->Nc = Nc; c->Mc = box_M(Nc);
   c->nf = nf; c->nc = nc;
   const size_t box = c->box_elems() * sizeof(cplx), rows = c->rows_elems() * sizeof(cplx);
@@ -463,7 +422,13 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   auto run_sweep = [&]() -> hipError_t {
     return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
   };
-  PD_HIP(c, run_sweep(), "coarse sweep");
+  const bool learned = c->lg.enabled && c->lg.init;
+  if (learned) {
+    pd_status ls = lg_sweep(c, 0, true, st);
+    if (ls != PD_OK) return ls;
+  } else {
+    PD_HIP(c, run_sweep(), "coarse sweep");
+  }
   PD_HIP(c, hipEventRecord(ev[1], st), "event");
   PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
   float ms = 0;
@@ -492,7 +457,12 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     // serial coarse sweep with the correction, then the defect sums
     sa.n0 = n0;
     sa.mode = 1;
-    PD_HIP(c, run_sweep(), "coarse sweep");
+    if (learned) {
+      pd_status ls = lg_sweep(c, n0, false, st);
+      if (ls != PD_OK) return ls;
+    } else {
+      PD_HIP(c, run_sweep(), "coarse sweep");
+    }
     PD_HIP(c, hipEventRecord(ev[2], st), "event");
     PD_HIP(c, hipMemcpyAsync(c->hred, c->red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
     PD_HIP(c, hipStreamSynchronize(st), "sync");
@@ -578,6 +548,8 @@ pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
 }
 
 // ---- autotuner --------------------------------------------------------------
+}  // extern "C"
+
 namespace {
 
 std::string tune_key(int device, int N, int P) {
@@ -636,6 +608,8 @@ void cache_store(const char* path, const std::string& key, int rv, int cv) {
 }
 
 }  // namespace
+
+extern "C" {
 
 pd_status pd_variant_info(int N, int kind, int v, int* a, int* b) {
   if (!a || !b || (kind != 0 && kind != 1)) return PD_EINVAL;

@@ -1,0 +1,160 @@
+"""GPU tests of the learned coarse propagator: BF16-MFMA forward and
+backward against the FP64 reference network, bitwise finite termination of
+learned-G Parareal, and the gain of the trained network over plain G."""
+import numpy as np
+import pytest
+
+from oracle import network as onet
+from synthetic import initial_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def relnorm(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def unflatten(p, Q, L, C=32):
+    o = 0
+    out = {}
+    for name, shape in (("W_in", (12, C)), ("V", (L, 3, 5, C, C)), ("gamma", (L, Q, C)),
+                        ("W_out", (C, 6))):
+        n = int(np.prod(shape))
+        out[name] = p[o:o + n].astype(np.float64).reshape(shape)
+        o += n
+    assert o == p.size
+    return out
+
+
+def small_ctx(lib, N=32, P=4, layers=2, seed=1):
+    ctx = lib.Context(0)
+    ctx.set_problem("gp", 50.0, 0.57, N)
+    ctx.set_time(1.0, P, 5e-3, 2.5e-2, N // 2)
+    ctx.lg_init(layers, seed)
+    return ctx
+
+
+def test_network_forward_and_gradients_match_fp64_reference(lib):
+    N, L = 32, 2
+    with small_ctx(lib, N=N, layers=L) as ctx:
+        D = np.stack([initial_field(N, 0.57, 40 + i, amp=1.0, kmax=6) for i in range(4)])
+        ctx.lg_add_samples(np.array([0.0, 0.25, 0.5, 0.75]), dev(D))
+        rng = np.random.default_rng(0)
+        p = ctx.lg_params()
+        Q = (2 * ((N - 1) // 3) + 1) ** 2
+        # make every parameter group matter (trained-like values)
+        p[-32 * 6:] = (rng.standard_normal(32 * 6) * 0.2).astype(np.float32)
+        ctx.lg_set_params(p)
+        prm = unflatten(p, Q, L)
+        xs, rs, ts = zip(*[ctx.lg_sample(i) for i in range(4)])
+        x = np.stack(xs).astype(np.float64)
+        r = np.stack(rs).astype(np.float64)
+        t = np.array(ts)
+        Mf = int(round(np.sqrt(Q)))
+        c_ref, _ = onet.forward(prm, x, t, Mf)
+        for i in range(4):
+            c_gpu = ctx.lg_forward_sample(i)
+            assert relnorm(c_gpu, c_ref[i]) <= 1e-2, (i, relnorm(c_gpu, c_ref[i]))
+        g_gpu, loss_gpu = ctx.lg_gradients(0, 4)
+        loss_ref, g_ref = onet.loss_and_grad(prm, x, t, r, Mf)
+        assert abs(loss_gpu - loss_ref) <= 1e-2 * loss_ref
+        gg = unflatten(g_gpu, Q, L)
+        for name in ("W_in", "V", "gamma", "W_out"):
+            assert relnorm(gg[name], g_ref[name]) <= 2e-2, (name, relnorm(gg[name], g_ref[name]))
+
+
+def test_learned_parareal_finite_termination_bitwise(lib):
+    torch = _torch()
+    N, P = 32, 4
+    with small_ctx(lib, N=N, P=P) as ctx:
+        b0 = initial_field(N, 0.57, 9)
+        ctx.set_coarse(True)
+        ctx.set_initial(b0)
+        rep = ctx.parareal(0.0, P + 1)
+        U = ctx.get_slices_dev()
+        u = dev(b0[None])
+        for n in range(P):
+            u = ctx.fine([n * 1.0 / P], u)
+            assert torch.equal(U[n + 1], u[0]), n
+        assert rep["sigma"][-1] == 0.0
+
+
+def test_parareal_samples_are_the_coarse_inputs(lib):
+    """The harvested samples of iteration 0 are U^0_n of the plain coarse run
+    and those of iteration 1 are U^1_n - U^0_n (n >= 1); the stored feature
+    x = D/|D| (FP32) reproduces them slice by slice, with the slice
+    start times."""
+    N, P = 32, 4
+    with small_ctx(lib, N=N, P=P) as ctx:
+        b0 = initial_field(N, 0.57, 21)
+        ctx.set_coarse(False)
+        ctx.set_initial(b0)
+        ctx.parareal(0.0, 0)
+        U0 = ctx.get_slices()
+        ctx.set_initial(b0)
+        ctx.parareal(0.0, 1)
+        U1 = ctx.get_slices()
+        ctx.set_initial(b0)
+        assert ctx.lg_add_parareal_samples(1) == P + (P - 1)
+        K = (N - 1) // 3
+        idx = np.r_[N - K:N, 0:K + 1]  # box rows/columns run over k = -K..K
+        expect = [U0[n] for n in range(P)] + [U1[n] - U0[n] for n in range(1, P)]
+        times = [float(n) / P for n in range(P)] + [float(n) / P for n in range(1, P)]
+        for i, (D, tn) in enumerate(zip(expect, times)):
+            x, _, t = ctx.lg_sample(i)
+            box = D[:, idx][:, :, idx]
+            Dn = box / np.linalg.norm(box)
+            xm = x.reshape(2 * K + 1, 2 * K + 1, 12)
+            got = (xm[..., 0:6:2] + 1j * xm[..., 1:6:2]).transpose(2, 0, 1)
+            assert relnorm(got, Dn) <= 1e-6, (i, relnorm(got, Dn))
+            assert abs(t - tn) <= 1e-12
+
+
+def test_trained_network_lowers_coarse_error_and_converges(lib):
+    """Train on the coarse inputs of plain-G Parareal runs (Galloway-Proctor
+    Rm = 100, 64^2, 16 slices of length 1, coarse 32^2 with dt = 1e-2) from
+    four initial fields; on a fifth run the relative one-slice error
+    |F - G_learned| / |F - G| drops, and learned-G Parareal from a sixth
+    field reaches sigma <= 1e-8 at the plain-G solution."""
+    N, Nc, P, Rm, kz = 64, 32, 16, 100.0, 0.57
+    with lib.Context(0) as ctx:
+        ctx.set_problem("gp", Rm, kz, N)
+        ctx.set_time(float(P), P, 2e-3, 1e-2, Nc)
+        ctx.lg_init(4, 3)
+        ctx.set_coarse(False)
+        n = 0
+        for r in range(5):
+            ntr = n
+            ctx.set_initial(initial_field(N, kz, 700 + r))
+            n = ctx.lg_add_parareal_samples(8)
+        val0 = ctx.lg_loss(ntr, n - ntr)
+        losses = ctx.lg_train(0, ntr, 800, 16, 2e-3, seed=11)
+        val1 = ctx.lg_loss(ntr, n - ntr)
+        print(f"held-out loss {val0:.3f} -> {val1:.3f}; last batch {losses[-1]:.3f}", flush=True)
+        assert abs(val0 - 1.0) < 0.05  # untrained output is ~1e-3 of the target
+        assert val1 < 0.7 * val0
+        b0 = initial_field(N, kz, 123)
+        ctx.set_coarse(False)
+        ctx.set_initial(b0)
+        rp = ctx.parareal(1e-8, P + 1)
+        Up = ctx.get_slices()
+        ctx.set_coarse(True)
+        ctx.set_initial(b0)
+        rl = ctx.parareal(1e-8, P + 1)
+        Ul = ctx.get_slices()
+        print(f"k_con plain {rp['k_con']} learned {rl['k_con']}; sigma plain "
+              f"{rp['sigma'][:rp['iters']]} learned {rl['sigma'][:rl['iters']]}", flush=True)
+        assert 0 < rp["k_con"] <= P + 1
+        assert 0 < rl["k_con"] <= P + 1
+        assert relnorm(Ul[P], Up[P]) <= 1e-7

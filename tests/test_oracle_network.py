@@ -1,0 +1,60 @@
+"""Pins of the FP64 reference network (learned coarse correction):
+manual gradients against central differences, linearity, G(0) = 0."""
+import numpy as np
+import pytest
+
+from oracle import network as net
+
+
+def tiny(seed=0, Mf=5, C=4, L=2, B=2):
+    rng = np.random.default_rng(seed)
+    p = net.init_params(Mf, C=C, L=L, seed=seed)
+    p["W_out"] = rng.standard_normal(p["W_out"].shape) * 0.3
+    p["gamma"] = 1.0 + 0.3 * rng.standard_normal(p["gamma"].shape)
+    x = rng.standard_normal((B, Mf * Mf, 12))
+    t = rng.uniform(0, 6, B)
+    r = rng.standard_normal((B, Mf * Mf, 6))
+    return p, x, t, r, Mf
+
+
+@pytest.mark.parametrize("name", ["W_in", "V", "gamma", "W_out"])
+def test_manual_gradients_match_central_differences(name):
+    p, x, t, r, Mf = tiny()
+    _, g = net.loss_and_grad(p, x, t, r, Mf)
+    rng = np.random.default_rng(1)
+    flat = p[name].reshape(-1)
+    for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+        h = 1e-6
+        old = flat[idx]
+        flat[idx] = old + h
+        lp, _ = net.loss_and_grad(p, x, t, r, Mf)
+        flat[idx] = old - h
+        lm, _ = net.loss_and_grad(p, x, t, r, Mf)
+        flat[idx] = old
+        fd = (lp - lm) / (2 * h)
+        an = g[name].reshape(-1)[idx]
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, an)
+
+
+def test_shift_convention():
+    Mf = 4
+    h = np.arange(Mf * Mf, dtype=float).reshape(1, Mf * Mf, 1)
+    s = net.shift_rows(h, Mf, 0, 1)            # out[m] = h[m + (0, +1)]
+    assert s[0, 0, 0] == 1 and s[0, Mf - 1, 0] == 0
+    s = net.shift_rows(h, Mf, 1, 0)            # out[m] = h[m + (+1, 0)]
+    assert s[0, 0, 0] == Mf and s[0, (Mf - 1) * Mf, 0] == 0
+
+
+def test_learned_propagator_is_linear_and_zero_at_zero():
+    rng = np.random.default_rng(3)
+    Mf = 7
+    p = net.init_params(Mf, C=4, L=2, seed=3)
+    p["W_out"] = rng.standard_normal(p["W_out"].shape)
+    D = rng.standard_normal((1, 3, Mf, Mf)) + 1j * rng.standard_normal((1, 3, Mf, Mf))
+    g = rng.standard_normal((1, 3, Mf, Mf)) + 1j * rng.standard_normal((1, 3, Mf, Mf))
+    t = np.array([1.3])
+    a = net.apply(p, D, g, t)
+    b = net.apply(p, 2.5 * D, 2.5 * g, t)
+    assert np.allclose(b, 2.5 * a, rtol=1e-12, atol=1e-12)
+    z = net.apply(p, 0 * D, 0 * g, t)
+    assert np.all(z == 0)
