@@ -138,6 +138,12 @@ pd_status pd_fine_dev(pd_ctx* ctx, const double* t0, int batch, const void* d_in
    Fourier re-sampling).  Same arguments as pd_fine_dev. */
 pd_status pd_coarse_dev(pd_ctx* ctx, const double* t0, int batch, const void* d_in, void* d_out,
                         void* hip_stream);
+/* F and G over one slice on host arrays: in, out [batch][3][N][N] complex
+   (interleaved re, im; may alias), t0[batch] host.  The same propagators as
+   pd_fine_dev / pd_coarse_dev, staged through device memory on the context's
+   stream. */
+pd_status pd_step_fine(pd_ctx* ctx, const double* t0, int batch, const double* in, double* out);
+pd_status pd_step_coarse(pd_ctx* ctx, const double* t0, int batch, const double* in, double* out);
 /* Any number of steps of size dt on the fine grid from t0[f] (no slice
    length needed): out = n_steps SBDF steps (first one SBDF1). */
 pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int n_steps,
@@ -151,6 +157,19 @@ pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int 
    results are unchanged bitwise.  `rep` may be NULL.  Returns PD_OK,
    PD_NOT_CONVERGED, or PD_EUNSTABLE if a defect sum is not finite. */
 pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
+
+/* Checkpoint and resume.  After k iterations of pd_parareal the whole state
+   of the iteration is the slice states U^k_n (pd_get_slices) and, for the
+   plain coarse propagator, the coarse values G(U^k_n), n = 0..P-1
+   (pd_get_coarse_values, full layout [P][3][N][N]).  pd_set_slices loads
+   such a state (U: [P+1][3][N][N]; Gold may be NULL when the learned coarse
+   propagator is selected, which needs none); the next pd_parareal then skips
+   the initial coarse run and goes on with iteration k + 1 up to max_iter
+   (> k), giving bitwise the results of the uninterrupted run.  Fields with
+   nonzero coefficients outside the 2/3 box are PD_EINVAL.  pd_set_initial
+   cancels a pending resume. */
+pd_status pd_get_coarse_values(const pd_ctx* ctx, double* out);
+pd_status pd_set_slices(pd_ctx* ctx, const double* U, const double* Gold, int k);
 
 /* Measurement helper: times the fine propagator on the context's slice
    buffers (inputs: the current slice states U_0..U_{P-1}; the results are
@@ -245,6 +264,13 @@ pd_status pd_lg_sample(pd_ctx* ctx, int i, float* x, float* r, double* t);
 pd_status pd_lg_forward_sample(pd_ctx* ctx, int i, float* out);
 /* Use the learned (1) or plain (0) coarse propagator in pd_parareal. */
 pd_status pd_set_coarse(pd_ctx* ctx, int learned);
+/* Save the network parameters to a file (8-byte magic "PDLGNET1", int32 N,
+   box width, layers, channels, uint64 count, FP32 values in the order of
+   pd_lg_params), or load such a file into a context with the same N (the
+   network is created with the file's layer count; stored samples and the
+   optimizer state are dropped).  PD_EINVAL on a file that does not match. */
+pd_status pd_lg_save(const pd_ctx* ctx, const char* path);
+pd_status pd_lg_load(pd_ctx* ctx, const char* path);
 
 /* ---- Many independent problems in one batch -------------------------------
  * Parareal (Section 3) for many (flow, Rm, kz, N) instances of uneven size at

@@ -42,6 +42,8 @@ SYMBOLS = [
     "pd_autotune", "pd_variant_info", "pd_select_variant",
     "pd_lg_init", "pd_lg_add_samples", "pd_lg_add_parareal_samples", "pd_lg_train", "pd_lg_loss", "pd_lg_gradients",
     "pd_lg_params", "pd_lg_set_params", "pd_lg_sample", "pd_lg_forward_sample", "pd_set_coarse",
+    "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
+    "pd_lg_load",
 ]
 
 
@@ -121,6 +123,12 @@ def _load():
         "pd_lg_sample": ([vp, i, C.POINTER(C.c_float), C.POINTER(C.c_float), dp], i),
         "pd_lg_forward_sample": ([vp, i, C.POINTER(C.c_float)], i),
         "pd_set_coarse": ([vp, i], i),
+        "pd_step_fine": ([vp, dp, i, dp, dp], i),
+        "pd_step_coarse": ([vp, dp, i, dp, dp], i),
+        "pd_get_coarse_values": ([vp, dp], i),
+        "pd_set_slices": ([vp, dp, dp, i], i),
+        "pd_lg_save": ([vp, C.c_char_p], i),
+        "pd_lg_load": ([vp, C.c_char_p], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +258,33 @@ class Context:
         d["status"] = st
         return d
 
+    def step_host(self, t0, b, fine: bool = True) -> np.ndarray:
+        """F (fine=True) or G over one slice of host fields [batch][3][N][N]."""
+        bb = np.ascontiguousarray(np.asarray(b, np.complex128).reshape(-1, 3, self.N, self.N))
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, np.float64), (bb.shape[0],)))
+        out = np.empty_like(bb)
+        fn = lib.pd_step_fine if fine else lib.pd_step_coarse
+        self._ok(fn(self._h, _dptr(t), bb.shape[0], _dptr(bb.view(np.float64)),
+                    _dptr(out.view(np.float64))))
+        return out
+
+    def get_coarse_values(self) -> np.ndarray:
+        out = np.empty((self.P, 3, self.N, self.N), np.complex128)
+        self._ok(lib.pd_get_coarse_values(self._h, _dptr(out.view(np.float64))))
+        return out
+
+    def set_slices(self, U, Gold, k: int):
+        """Resume: the next parareal() goes on after iteration k from U (and
+        the coarse values Gold, None for the learned coarse propagator)."""
+        Ub = np.ascontiguousarray(np.asarray(U, np.complex128))
+        assert Ub.shape == (self.P + 1, 3, self.N, self.N)
+        gp = None
+        if Gold is not None:
+            Gb = np.ascontiguousarray(np.asarray(Gold, np.complex128))
+            assert Gb.shape == (self.P, 3, self.N, self.N)
+            gp = _dptr(Gb.view(np.float64))
+        self._ok(lib.pd_set_slices(self._h, _dptr(Ub.view(np.float64)), gp, int(k)))
+
     def get_slices(self) -> np.ndarray:
         out = np.empty((self.P + 1, 3, self.N, self.N), np.complex128)
         self._ok(lib.pd_get_slices(self._h, _dptr(out.view(np.float64))))
@@ -284,6 +319,12 @@ class Context:
     # -- learned coarse propagator -------------------------------------------
     def lg_init(self, layers: int = 4, seed: int = 0):
         self._ok(lib.pd_lg_init(self._h, int(layers), C.c_uint64(seed)))
+
+    def lg_save(self, path: str):
+        self._ok(lib.pd_lg_save(self._h, str(path).encode()))
+
+    def lg_load(self, path: str):
+        self._ok(lib.pd_lg_load(self._h, str(path).encode()))
 
     def lg_add_samples(self, t0, D):
         _check_dev(D, self.N)

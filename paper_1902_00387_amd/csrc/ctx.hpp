@@ -31,6 +31,8 @@ struct pd_ctx {
   double T = 0, dT = 0, dtf = 0, dtc = 0;
   int P = 0, Nc = 0, Mc = 0, nf = 0, nc = 0;
   bool have_initial = false;
+  int resume_k = -1;                   // pd_set_slices: the next pd_parareal goes on after iteration k
+  bool have_gold = false;              // the resumed state came with the previous coarse values
   // device memory
   DevBuf tw, twc;                      // twiddles (fine, coarse)
   DevBuf U, Fo, Gold, Hf, T1f, T2f;    // slice buffers

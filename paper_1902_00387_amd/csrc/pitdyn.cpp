@@ -234,6 +234,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   if (!valid_N(N)) return fail(c, PD_EINVAL, "N must be one of 16, 32, 64, 128, 256, 512");
   DeviceGuard dg(c->device);
   c->have_problem = c->have_time = c->have_initial = false;
+  c->resume_k = -1;
   lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
   c->T2f.release(); c->Uprev.release();
@@ -264,6 +265,7 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   if (!integer_ratio(dT, dtc, &nc)) return fail(c, PD_EINVAL, "slice length is not an integer number of coarse steps");
   DeviceGuard dg(c->device);
   c->have_time = c->have_initial = false;
+  c->resume_k = -1;
   lg_release(c);
   c->T = T; c->P = P; c->dT = dT; c->dtf = dtf; c->dtc = dtc; c->Nc = Nc; c->Mc = box_M(Nc);
   c->nf = nf; c->nc = nc;
@@ -323,6 +325,7 @@ pd_status pd_set_initial_dev(pd_ctx* c, const void* d_b0, void* s) {
   PD_HIP(c, pd::pack(static_cast<const cplx*>(d_b0), c->U.as<cplx>(), c->N, c->M, 1, st), "pack");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   c->have_initial = true;
+  c->resume_k = -1;
   return PD_OK;
 }
 
@@ -348,6 +351,7 @@ pd_status pd_set_initial(pd_ctx* c, const double* b0) {
   PD_HIP(c, pd::pack(tmp.as<cplx>(), c->U.as<cplx>(), N, c->M, 1, c->stream), "pack");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
   c->have_initial = true;
+  c->resume_k = -1;
   return PD_OK;
 }
 
@@ -387,6 +391,14 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   const int P = c->P;
   cplx* U = c->U.as<cplx>();
   cplx* Fo = c->Fo.as<cplx>();
+  // resumed run (pd_set_slices): U holds U^k, Gold holds G(U^k_n)
+  const int kres = c->resume_k;
+  const bool learned = c->lg.enabled && c->lg.init;
+  if (kres >= 0 && !learned && !c->have_gold)
+    return fail(c, PD_EINVAL, "resuming plain-G Parareal needs the coarse values (pd_set_slices Gold)");
+  if (kres >= 0 && max_iter <= kres)
+    return fail(c, PD_EINVAL, "max_iter must exceed the resumed iteration %d", kres);
+  c->resume_k = -1;
   pd_report r;
   std::memset(&r, 0, sizeof r);
   r.k_con = -1;
@@ -422,8 +434,9 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   auto run_sweep = [&]() -> hipError_t {
     return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
   };
-  const bool learned = c->lg.enabled && c->lg.init;
-  if (learned) {
+  if (kres >= 0) {
+    // nothing to do: the state of iteration kres was supplied
+  } else if (learned) {
     pd_status ls = lg_sweep(c, 0, true, st);
     if (ls != PD_OK) return ls;
   } else {
@@ -436,7 +449,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   r.t_coarse0_s = ms * 1e-3;
 
   pd_status status = PD_NOT_CONVERGED;
-  for (int k = 1; k <= max_iter; ++k) {
+  for (int k = kres >= 0 ? kres + 1 : 1; k <= max_iter; ++k) {
     const int n0 = k - 1 < P - 1 ? k - 1 : P - 1;
     PD_HIP(c, hipMemcpyAsync(c->Uprev.p, U + (size_t)P * box, box * sizeof(cplx),
                              hipMemcpyDeviceToDevice, st), "copy");

@@ -1,0 +1,123 @@
+"""GPU tests of the host-array propagator calls, Parareal checkpoint and
+resume, and the parameter file of the learned coarse propagator."""
+import numpy as np
+import pytest
+
+from oracle import stepper
+from synthetic import initial_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def problem(ctx, N=32, P=6, flow="gp"):
+    ctx.set_problem(flow, 50.0, 0.57, N)
+    ctx.set_time(1.5, P, 5e-3, 2.5e-2, N // 2)
+
+
+def test_host_steps_equal_device_steps_and_oracle(lib):
+    torch = _torch()
+    N = 32
+    with lib.Context(0) as ctx:
+        problem(ctx, N=N)
+        b = np.stack([initial_field(N, 0.57, s) for s in (1, 2, 3)])
+        t0 = np.array([0.0, 0.25, 0.75])
+        for fine in (True, False):
+            h = ctx.step_host(t0, b, fine=fine)
+            d = (ctx.fine if fine else ctx.coarse)(t0, torch.from_numpy(b).cuda()).cpu().numpy()
+            assert np.array_equal(h, d)
+        ref = stepper.SliceSolver("gp", 50.0, 0.57, N, 0.25, 5e-3)(b[1], 0.25)
+        got = ctx.step_host(t0[1:2], b[1:2])[0]
+        assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_checkpoint_resume_is_bitwise(lib, learned):
+    N, P, tol = 32, 6, 1e-10
+    b0 = initial_field(N, 0.57, 31)
+    with lib.Context(0) as ctx:
+        problem(ctx, N=N, P=P)
+        if learned:
+            ctx.lg_init(2, 7)
+            p = ctx.lg_params()
+            p[-32 * 6:] = np.random.default_rng(3).standard_normal(32 * 6).astype(np.float32) * 0.05
+            ctx.lg_set_params(p)
+            ctx.set_coarse(True)
+        ctx.set_initial(b0)
+        full = ctx.parareal(tol, P + 1)
+        U_full = ctx.get_slices()
+        assert full["k_con"] > 3
+        ctx.set_initial(b0)
+        part = ctx.parareal(0.0, 3)
+        U3 = ctx.get_slices()
+        G3 = None if learned else ctx.get_coarse_values()
+        assert part["sigma"][:3] == full["sigma"][:3]
+        # a second context stands for a restarted process
+        with lib.Context(0) as c2:
+            problem(c2, N=N, P=P)
+            if learned:
+                c2.lg_init(2, 7)
+                c2.lg_set_params(ctx.lg_params())
+                c2.set_coarse(True)
+            c2.set_slices(U3, G3, 3)
+            rest = c2.parareal(tol, P + 1)
+            assert rest["k_con"] == full["k_con"]
+            assert rest["sigma"][3:rest["iters"]] == full["sigma"][3:full["iters"]]
+            assert np.array_equal(c2.get_slices(), U_full)
+
+
+def test_resume_argument_errors(lib):
+    N, P = 32, 6
+    with lib.Context(0) as ctx:
+        problem(ctx, N=N, P=P)
+        ctx.set_initial(initial_field(N, 0.57, 5))
+        ctx.parareal(0.0, 2)
+        U = ctx.get_slices()
+        G = ctx.get_coarse_values()
+        ctx.set_slices(U, None, 2)
+        with pytest.raises(lib.PitdynError):
+            ctx.parareal(0.0, 4)  # plain G needs the coarse values
+        ctx.set_slices(U, G, 2)
+        with pytest.raises(lib.PitdynError):
+            ctx.parareal(0.0, 2)  # nothing after iteration 2
+        bad = U.copy()
+        bad[1, 0, N // 2, 0] = 1.0  # outside the 2/3 box
+        with pytest.raises(lib.PitdynError):
+            ctx.set_slices(bad, G, 2)
+        ctx.set_slices(U, G, 2)
+        ctx.set_initial(U[0])  # cancels the resume
+        r = ctx.parareal(0.0, 2)
+        assert r["iters"] == 2
+
+
+def test_learned_parameter_file_round_trip(lib, tmp_path):
+    N = 32
+    path = tmp_path / "net.bin"
+    with lib.Context(0) as ctx:
+        problem(ctx, N=N)
+        ctx.lg_init(3, 11)
+        p = ctx.lg_params()
+        p += np.random.default_rng(0).standard_normal(p.size).astype(np.float32) * 0.01
+        ctx.lg_set_params(p)
+        ctx.lg_save(path)
+        with lib.Context(0) as c2:
+            problem(c2, N=N)
+            c2.lg_load(path)
+            assert np.array_equal(c2.lg_params(), p)
+        with lib.Context(0) as c3:
+            problem(c3, N=64)
+            with pytest.raises(lib.PitdynError):
+                c3.lg_load(path)  # other grid
+        raw = path.read_bytes()
+        (tmp_path / "short.bin").write_bytes(raw[:-4])
+        (tmp_path / "magic.bin").write_bytes(b"XXXXXXXX" + raw[8:])
+        with lib.Context(0) as c4:
+            problem(c4, N=N)
+            for bad in ("short.bin", "magic.bin", "missing.bin"):
+                with pytest.raises(lib.PitdynError):
+                    c4.lg_load(tmp_path / bad)
