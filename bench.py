@@ -197,6 +197,129 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_workload():
+    """Learned-versus-plain coarse propagator: Galloway-Proctor flow, Rm = 500,
+    kz = 0.57, 256 x 256, T = 64 over 128 slices (slice length 0.5), fine
+    SBDF2 dt = 1e-3."""
+    return dict(N=256, Rm=500.0, kz=0.57, T=64.0, P=128, dtf=1e-3, seed=400000)
+
+
+def coarse_choice(ctx, w, b0, fine_norm_T):
+    """Largest N_C in {N/2, N/4} and Delta t in {1e-2, 5e-3, 2.5e-3} (halved
+    until one passes) whose initial coarse run over [0, T] stays finite and
+    within 1e3 of the fine solution's norm at T."""
+    import numpy as np
+    for dtc in (1e-2, 5e-3, 2.5e-3):
+        for nc in (w["N"] // 2, w["N"] // 4):
+            ctx.set_time(w["T"], w["P"], w["dtf"], dtc, nc)
+            ctx.set_initial(b0)
+            ctx.parareal(0.0, 0)
+            nrm = ctx.slice_norms()
+            ok = bool(np.all(np.isfinite(nrm))) and nrm[-1] <= 1e3 * fine_norm_T
+            print(f"# coarse pre-check N_C={nc} dt={dtc}: |U_P|={nrm[-1]:.3e} "
+                  f"(fine {fine_norm_T:.3e}) {'ok' if ok else 'rejected'}", file=sys.stderr, flush=True)
+            if ok:
+                return nc, dtc
+    raise RuntimeError("no stable coarse propagator among the candidates")
+
+
+def run_learned(args):
+    """Time to sigma <= 1e-8 with the plain and the learned coarse propagator
+    (plus the serial fine solve on the same GPU), and the training cost."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+    import numpy as np
+    w = learned_workload()
+    N, P, T = w["N"], w["P"], w["T"]
+    nf = int(round(T / P / w["dtf"]))
+    dev = torch.device("cuda:0")
+    b0 = torch.from_numpy(initial_field(N, w["kz"], w["seed"])).to(dev)
+    ctx = pd.Context(0)
+    ctx.set_problem("gp", w["Rm"], w["kz"], N)
+    ctx.set_time(T, P, w["dtf"], 1e-2, N // 2)
+    # serial fine solve (slices one after another, batch 1)
+    u = b0[None].clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for n in range(P):
+        u = ctx.fine([n * T / P], u)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - ts
+    fine_norm_T = float(torch.linalg.vector_norm(u).item())
+    print(f"# serial fine solve {serial_s:.2f} s, |b(T)| = {fine_norm_T:.3e}", file=sys.stderr, flush=True)
+    nc, dtc = coarse_choice(ctx, w, b0, fine_norm_T)
+    ctx.set_time(T, P, w["dtf"], dtc, nc)
+
+    def solve(learned):
+        ctx.set_coarse(learned)
+        ctx.set_initial(b0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.parareal(TOL, P + 1)
+        gam = ctx.growth_rate()
+        torch.cuda.synchronize()
+        return rep, gam, time.perf_counter() - t0
+
+    solve(False)
+    rp, gp, tp = solve(False)
+    Up = ctx.get_slices_dev()[P].clone()
+    print(f"# plain G: k_con {rp['k_con']} in {tp:.2f} s", file=sys.stderr, flush=True)
+    # training pairs from the fine and coarse propagators
+    rng = np.random.default_rng(w["seed"] + 1)
+    ctx.lg_init(4, w["seed"])
+    tg = time.perf_counter()
+    n_fields = 512
+    for a in range(0, n_fields, 64):
+        D = np.stack([initial_field(N, w["kz"], w["seed"] + 10 + i, amp=1.0,
+                                    kmax=float(rng.uniform(2.0, 40.0))) for i in range(a, a + 64)])
+        tt = rng.integers(0, P, D.shape[0]) * (T / P)
+        ctx.lg_add_samples(tt, torch.from_numpy(D).to(dev))
+    for r in range(2):
+        ctx.set_coarse(False)
+        ctx.set_initial(torch.from_numpy(initial_field(N, w["kz"], w["seed"] + 1000 + r)).to(dev))
+        n_samples = ctx.lg_add_parareal_samples(3)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - tg
+    print(f"# {n_samples} training pairs in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    n_val = 64
+    ttr = time.perf_counter()
+    val0 = ctx.lg_loss(n_samples - n_val, n_val)
+    steps = 1500
+    losses = ctx.lg_train(0, n_samples - n_val, steps, 8, 1e-3, seed=5)
+    val1 = ctx.lg_loss(n_samples - n_val, n_val)
+    train_s = time.perf_counter() - ttr
+    print(f"# training {steps} steps {train_s:.1f} s: held-out loss {val0:.3f} -> {val1:.3f}",
+          file=sys.stderr, flush=True)
+    solve(True)
+    rl, gl, tl = solve(True)
+    Ul = ctx.get_slices_dev()[P]
+    diff = float(torch.linalg.vector_norm(Ul - Up).item() / torch.linalg.vector_norm(Up).item())
+    print(f"# learned G: k_con {rl['k_con']} in {tl:.2f} s", file=sys.stderr, flush=True)
+    ctx.close()
+    out = {
+        "metric": "time to Parareal defect <= 1e-8, learned vs plain coarse propagator",
+        "value": tl, "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "c128 fine / bf16-fp32 network", "data": "synthetic",
+        "config": {"workload": "Galloway-Proctor Rm=500, kz=0.57, 256x256, T=64 over 128 slices, "
+                               f"fine SBDF2 dt=1e-3 ({nf} steps a slice), coarse SBDF2 on {nc}^2 dt={dtc}, "
+                               "network 4 layers width 32",
+                   "N_coarse": nc, "dt_coarse": dtc},
+        "plain": {"k_con": rp["k_con"], "time_s": tp, "growth_rate": gp,
+                  "t_fine_s": rp["t_fine_s"], "t_coarse_s": rp["t_coarse_s"] + rp["t_coarse0_s"],
+                  "sigma": rp["sigma"][:rp["iters"]]},
+        "learned": {"k_con": rl["k_con"], "time_s": tl, "growth_rate": gl,
+                    "t_fine_s": rl["t_fine_s"], "t_coarse_s": rl["t_coarse_s"] + rl["t_coarse0_s"],
+                    "sigma": rl["sigma"][:rl["iters"]], "final_state_reldiff_vs_plain": diff},
+        "serial_fine_gpu_s": serial_s,
+        "speedup_vs_serial": {"plain": serial_s / tp, "learned": serial_s / tl},
+        "training": {"pairs": n_samples, "generate_s": gen_s, "train_s": train_s, "steps": steps,
+                     "batch": 8, "held_out_loss": [val0, val1], "last_batch_loss": losses[-1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +331,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the many-instance workload instead of the single solve")
     ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--learned", action="store_true",
+                    help="learned versus plain coarse propagator (256^2, 128 slices)")
     ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs")
@@ -229,6 +354,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch:
         run_batch(args)
+        return
+    if args.learned:
+        run_learned(args)
         return
     dev = torch.device("cuda:0")
     b0 = torch.from_numpy(initial_field(N, KZ, SEED)).to(dev)

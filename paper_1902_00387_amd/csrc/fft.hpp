@@ -109,12 +109,61 @@ __device__ __forceinline__ void group_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Pass plan of a length-N transform with E values a lane: pass p has radix
+// R(p) and combines sub-transforms of length NS(p).
+//   E = 8: 16: 8x2   32: 8x4   64: 8x8   128: 8x8x2   256: 8x8x4   512: 8x8x8
+//   E = 4: 16: 4x4   32: 4x4x2   64: 4x4x4   128: 4x4x4x2   256: 4x4x4x4
+template <int N, int E>
+struct Plan {
+  static_assert(N >= 16 && N <= 512 && (N & (N - 1)) == 0, "N");
+  static_assert((E == 8 && N / E <= 64) || (E == 4 && N / E <= 64), "group must fit a wavefront");
+  static constexpr int passes = E == 8 ? (N <= 64 ? 2 : 3) : (N == 16 ? 2 : (N <= 64 ? 3 : 4));
+  static constexpr int R(int p) {
+    return E == 8 ? (p == 0 ? 8 : p == 1 ? (N == 16 ? 2 : N == 32 ? 4 : 8) : N / 64)
+                  : (p <= 1 ? 4 : p == 2 ? (N == 32 ? 2 : 4) : N / 64);
+  }
+  static constexpr int NS(int p) { return p == 0 ? 1 : p == 1 ? E : p == 2 ? (E == 8 ? 64 : 16) : 64; }
+  // twiddles a lane needs in pass p: R - 1 for each of its E/R butterflies
+  static constexpr int tw_count(int p) { return NS(p) > 1 ? (E / R(p)) * (R(p) - 1) : 0; }
+  static constexpr int tw_total() {
+    int t = 0;
+    for (int p = 0; p < passes; ++p) t += tw_count(p);
+    return t;
+  }
+};
+
+// The twiddles of every pass of one transform for one lane, read once from
+// the table and then kept in registers (forward convention e^{-2 pi i m/N};
+// the inverse uses their conjugates).  Loading them ahead keeps global-memory
+// latency out of the passes, which the LDS exchange orders.
+template <int N, int E>
+struct TwRegs {
+  using PL = Plan<N, E>;
+  static constexpr int count = PL::tw_total();
+  cplx w[count > 0 ? count : 1];
+  __device__ __forceinline__ void load(int j, const cplx* __restrict__ tw) {
+    constexpr int T = N / E;
+    int o = 0;
+#pragma unroll
+    for (int p = 0; p < PL::passes; ++p) {
+      const int R = PL::R(p), NS = PL::NS(p);
+      if (NS == 1) continue;
+#pragma unroll
+      for (int q = 0; q < E / R; ++q) {
+        const int jj = (j + T * q) & (NS - 1);
+#pragma unroll
+        for (int k = 1; k < R; ++k) w[o++] = tw[jj * k * (N / (NS * R))];
+      }
+    }
+  }
+};
+
 // One Stockham pass of radix R over sub-transforms of length NS, E values a
-// lane.  Lane j owns butterflies b = j + T*q, q < E/R (T = N/E lanes).
-// Outputs are scattered to LDS (padded), then the lane reads back its
-// strided values.
+// lane.  Lane j owns butterflies b = j + T*q, q < E/R (T = N/E lanes); wl
+// holds its (E/R) * (R-1) twiddles of this pass.  Outputs are scattered to
+// LDS (padded), then the lane reads back its strided values.
 template <int N, int E, int R, int NS, int DIR>
-__device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* __restrict__ tw) {
+__device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* wl) {
   constexpr int T = N / E, Q = E / R;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -126,7 +175,7 @@ __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* __
     if constexpr (NS > 1) {
 #pragma unroll
       for (int k = 1; k < R; ++k) {
-        const cplx w = tw[jj * k * (N / (NS * R))];
+        const cplx w = wl[q * (R - 1) + k - 1];
         x[k] = (DIR < 0) ? cmul(x[k], w) : cmulc(x[k], w);
       }
     }
@@ -141,35 +190,29 @@ __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* __
   group_sync();
 }
 
+template <int N, int E, int P, int DIR>
+__device__ __forceinline__ void fft_from(cplx* v, cplx* s, int j, const cplx* w) {
+  using PL = Plan<N, E>;
+  if constexpr (P < PL::passes) {
+    fft_pass<N, E, PL::R(P), PL::NS(P), DIR>(v, s, j, w);
+    fft_from<N, E, P + 1, DIR>(v, s, j, w + PL::tw_count(P));
+  }
+}
+
 // Full length-N transform of the strided register vector v (E values a
 // lane, T = N/E lanes, all in one wavefront; see header).  s: this group's
-// LDS span (LdsSpan<N>::value entries).
-//   E = 8: 16: 8x2   32: 8x4   64: 8x8   128: 8x8x2   256: 8x8x4   512: 8x8x8
-//   E = 4: 16: 4x4   32: 4x4x2   64: 4x4x4   128: 4x4x4x2   256: 4x4x4x4
+// LDS span (LdsSpan<N>::value entries); t: the lane's twiddles (TwRegs).
+template <int N, int E, int DIR>
+__device__ __forceinline__ void fft(cplx* v, cplx* s, int j, const TwRegs<N, E>& t) {
+  fft_from<N, E, 0, DIR>(v, s, j, t.w);
+}
+
+// Same, reading the lane's twiddles from the table first.
 template <int N, int E, int DIR>
 __device__ __forceinline__ void fft(cplx* v, cplx* s, int j, const cplx* __restrict__ tw) {
-  static_assert(N >= 16 && N <= 512 && (N & (N - 1)) == 0, "N");
-  static_assert((E == 8 && N / E <= 64) || (E == 4 && N / E <= 64), "group must fit a wavefront");
-  if constexpr (E == 8) {
-    fft_pass<N, 8, 8, 1, DIR>(v, s, j, tw);
-    if constexpr (N == 16) fft_pass<N, 8, 2, 8, DIR>(v, s, j, tw);
-    else if constexpr (N == 32) fft_pass<N, 8, 4, 8, DIR>(v, s, j, tw);
-    else {
-      fft_pass<N, 8, 8, 8, DIR>(v, s, j, tw);
-      if constexpr (N == 128) fft_pass<N, 8, 2, 64, DIR>(v, s, j, tw);
-      else if constexpr (N == 256) fft_pass<N, 8, 4, 64, DIR>(v, s, j, tw);
-      else if constexpr (N == 512) fft_pass<N, 8, 8, 64, DIR>(v, s, j, tw);
-    }
-  } else {
-    fft_pass<N, 4, 4, 1, DIR>(v, s, j, tw);
-    fft_pass<N, 4, 4, 4, DIR>(v, s, j, tw);
-    if constexpr (N == 32) fft_pass<N, 4, 2, 16, DIR>(v, s, j, tw);
-    else if constexpr (N >= 64) {
-      fft_pass<N, 4, 4, 16, DIR>(v, s, j, tw);
-      if constexpr (N == 128) fft_pass<N, 4, 2, 64, DIR>(v, s, j, tw);
-      else if constexpr (N == 256) fft_pass<N, 4, 4, 64, DIR>(v, s, j, tw);
-    }
-  }
+  TwRegs<N, E> t;
+  t.load(j, tw);
+  fft_from<N, E, 0, DIR>(v, s, j, t.w);
 }
 
 }  // namespace pd

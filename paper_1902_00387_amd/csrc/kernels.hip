@@ -82,6 +82,8 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
                                           const Problem& pb, int mode, bool last) {
   using G = Geo<N, E>;
   constexpr int T = G::T, K = G::K, M = G::M;
+  TwRegs<N, E> twr;
+  twr.load(j, tw);
   cplx w[3][E];
   const int ky = r - K;
   if (mode == 0) {
@@ -99,7 +101,7 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 #pragma unroll
       for (int e = 0; e < E; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : czero();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, tw);
+    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, twr);
     const double sc = 1.0 / ((double)N * (double)N);
     const double dt = pb.dt, kz = pb.kz;
 #pragma unroll
@@ -140,7 +142,7 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
   if (!last) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      fft<N, E, 1>(w[c], s, j, tw);
+      fft<N, E, 1>(w[c], s, j, twr);
       if (active) {
 #pragma unroll
         for (int e = 0; e < E; ++e) T1[(c * M + r) * N + j + T * e] = w[c][e];
@@ -155,7 +157,7 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 // (pitch TX + 1) so that global loads and stores run along x and all three
 // are in flight at once; once every group holds its column in registers the
 // tile memory doubles as the groups' FFT exchange spans.
-template <int N, int E, int LANES>
+template <int N, int E, int LANES, int CH>
 __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restrict__ T1,
                                          cplx* __restrict__ T2, const cplx* __restrict__ tw,
                                          const FlowPhase& fp) {
@@ -170,10 +172,29 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
   const int x = x0 + g;
   const bool active = g < TX && x < N;
   cplx* s = tile + (g < TX ? g : 0) * G::SPAN;
-  for (int i = tid; i < 3 * M * TX; i += nthr) {
-    const int c = i / (M * TX), rem = i - c * (M * TX);
-    const int r = rem / TX, cc = rem - r * TX;
-    tile[c * TS + r * TP + cc] = (x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : czero();
+  TwRegs<N, E> twr;
+  twr.load(j, tw);
+  // each lane issues a chunk of CH tile loads before the chunk's LDS
+  // stores, so the workgroup waits for global memory once a chunk, not once
+  // per element (CH bounded by register pressure)
+  constexpr int NIT = (3 * M * TX + nthr - 1) / nthr;
+#pragma unroll 1
+  for (int i0 = 0; i0 < NIT; i0 += CH) {
+    cplx buf[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int i = tid + (i0 + q) * nthr;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      buf[q] = (i0 + q < NIT && i < 3 * M * TX && x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : czero();
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int i = tid + (i0 + q) * nthr;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      if (i0 + q < NIT && i < 3 * M * TX) tile[c * TS + r * TP + cc] = buf[q];
+    }
   }
   __syncthreads();
   cplx w[3][E];
@@ -187,7 +208,7 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
   __syncthreads();
   if (g < TX) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fft<N, E, 1>(w[c], s, j, tw);
+    for (int c = 0; c < 3; ++c) fft<N, E, 1>(w[c], s, j, twr);
     // E = u x b at (x, y_e)
     const int xa = active ? x : 0;
     const double cx = tw[xa].re, sx = -tw[xa].im;
@@ -206,7 +227,7 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
       w[2][e] = csub(cscale(by, ux), cscale(bx, uy));
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, tw);
+    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, twr);
   }
   __syncthreads();
   if (g < TX) {
@@ -219,10 +240,23 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
       }
   }
   __syncthreads();
-  for (int i = tid; i < 3 * M * TX; i += nthr) {
-    const int c = i / (M * TX), rem = i - c * (M * TX);
-    const int r = rem / TX, cc = rem - r * TX;
-    if (x0 + cc < N) T2[(c * M + r) * N + x0 + cc] = tile[c * TS + r * TP + cc];
+#pragma unroll 1
+  for (int i0 = 0; i0 < NIT; i0 += CH) {
+    cplx buf[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int i = tid + (i0 + q) * nthr;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      buf[q] = (i0 + q < NIT && i < 3 * M * TX) ? tile[c * TS + r * TP + cc] : czero();
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int i = tid + (i0 + q) * nthr;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      if (i0 + q < NIT && i < 3 * M * TX && x0 + cc < N) T2[(c * M + r) * N + x0 + cc] = buf[q];
+    }
   }
   __syncthreads();
 }
@@ -270,7 +304,8 @@ __attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb
   const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
   const size_t rows = (size_t)3 * G::M * N;
   const FlowPhase fp = flow_phase(pb, fb.t0[f] + step * pb.dt);
-  col_tile<N, E, TX * G::T>(blockIdx.x * TX, tile, fb.T1 + f * rows, fb.T2 + f * rows, fb.tw, fp);
+  col_tile<N, E, TX * G::T, E == 8 ? 8 : 4>(blockIdx.x * TX, tile, fb.T1 + f * rows,
+                                            fb.T2 + f * rows, fb.tw, fp);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +343,7 @@ __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* 
   __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
     const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
-    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L>(x0, tile, T1, T2, tw, fp);
+    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
     const int mode = step == 0 ? 1 : 2;
     const bool last = step == nsteps - 1;
     for (int r0 = 0; r0 < M; r0 += NGR)
