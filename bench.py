@@ -334,6 +334,10 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="learned versus plain coarse propagator (256^2, 128 slices)")
     ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
+    ap.add_argument("--pipeline", type=int, default=-1,
+                    help="slice chunks of pipelined Parareal (0/1 off, -1 library default)")
+    ap.add_argument("--pipeline-hold-last", action="store_true",
+                    help="pipelined: start the next fine sweep's last chunk only after the defect")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs")
     args = ap.parse_args()
@@ -364,6 +368,8 @@ def main():
     ctx.set_problem("gp", RM, KZ, N)
     ctx.set_time(T, P, DT_FINE, DT_COARSE, N_COARSE)
     ctx.set_path(args.path)
+    if args.pipeline >= 0:
+        ctx.set_pipeline(args.pipeline, not args.pipeline_hold_last)
     nf = int(round(T / P / DT_FINE))
     # launch shapes of the fine step's kernels, picked by timing on this device
     ctx.set_initial(b0)

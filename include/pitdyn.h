@@ -158,6 +158,21 @@ pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int 
    PD_NOT_CONVERGED, or PD_EUNSTABLE if a defect sum is not finite. */
 pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
 
+/* Order of the work inside pd_parareal with the plain coarse propagator.
+   chunks >= 2: pipelined -- the serial coarse sweep runs on a stream of its
+   own in `chunks` runs of consecutive slices, and the fine sweep of a run of
+   slices (on one of two fine streams) starts as soon as the coarse sweep has
+   produced its start values, so the fine sweeps of iteration k + 1 overlap
+   the coarse sweep of iteration k.  They start before the defect of
+   iteration k is known: every run with speculate_all != 0, all but the last
+   run otherwise; when the iteration stops at k, the call still waits for
+   them and discards their results.  chunks 0 or 1 (the default): every fine
+   sweep, then the coarse sweep, on the context's stream.  Both orders give
+   bitwise the same iterates, defects and k_con; the timings in pd_report add
+   kernel times per stream (they overlap when pipelined).  The learned coarse
+   propagator always runs unpipelined. */
+pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate_all);
+
 /* Checkpoint and resume.  After k iterations of pd_parareal the whole state
    of the iteration is the slice states U^k_n (pd_get_slices) and, for the
    plain coarse propagator, the coarse values G(U^k_n), n = 0..P-1

@@ -43,7 +43,7 @@ SYMBOLS = [
     "pd_lg_init", "pd_lg_add_samples", "pd_lg_add_parareal_samples", "pd_lg_train", "pd_lg_loss", "pd_lg_gradients",
     "pd_lg_params", "pd_lg_set_params", "pd_lg_sample", "pd_lg_forward_sample", "pd_set_coarse",
     "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
-    "pd_lg_load",
+    "pd_lg_load", "pd_set_pipeline",
 ]
 
 
@@ -129,6 +129,7 @@ def _load():
         "pd_set_slices": ([vp, dp, dp, i], i),
         "pd_lg_save": ([vp, C.c_char_p], i),
         "pd_lg_load": ([vp, C.c_char_p], i),
+        "pd_set_pipeline": ([vp, i, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +268,10 @@ class Context:
         self._ok(fn(self._h, _dptr(t), bb.shape[0], _dptr(bb.view(np.float64)),
                     _dptr(out.view(np.float64))))
         return out
+
+    def set_pipeline(self, chunks: int, speculate_all: bool = True):
+        """Pipelined Parareal over `chunks` runs of slices (0 or 1: off)."""
+        self._ok(lib.pd_set_pipeline(self._h, int(chunks), int(bool(speculate_all))))
 
     def get_coarse_values(self) -> np.ndarray:
         out = np.empty((self.P, 3, self.N, self.N), np.complex128)

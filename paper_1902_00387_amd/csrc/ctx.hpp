@@ -18,6 +18,11 @@ struct pd_ctx {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;      // second stream of the two-stream fine sweep
   hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
+  hipStream_t cst = nullptr;       // pipelined Parareal: coarse sweep stream
+  hipStream_t fst = nullptr;       // pipelined Parareal: fine streams
+  hipStream_t fst2 = nullptr;
+  int pipe_spec = 1;               // pipelined: start every chunk of the next fine sweep early
+  int pipe_chunks = 0;             // slice chunks of the pipelined Parareal (< 2: off)
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;
@@ -93,6 +98,8 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
 // learned coarse propagator (lg.cpp)
 void lg_release(pd_ctx* c);
 pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st);
+// pipelined Parareal with the plain coarse propagator (pipeline.cpp)
+pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep);
 
 }  // namespace ctxh
 }  // namespace pd

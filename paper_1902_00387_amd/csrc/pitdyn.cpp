@@ -184,6 +184,11 @@ void pd_destroy(pd_ctx* c) {
       (void)hipStreamSynchronize(c->side);
       (void)hipStreamDestroy(c->side);
     }
+    for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2})
+      if (*p) {
+        (void)hipStreamSynchronize(*p);
+        (void)hipStreamDestroy(*p);
+      }
     for (auto& e : c->sev)
       if (e) (void)hipEventDestroy(e);
     if (c->hred) (void)hipHostFree(c->hred);
@@ -203,6 +208,14 @@ const char* pd_last_error(const pd_ctx* c) { return c ? c->err.c_str() : "null c
 pd_status pd_set_stream(pd_ctx* c, void* s) {
   if (!c) return PD_EINVAL;
   c->stream = s ? static_cast<hipStream_t>(s) : c->own;
+  return PD_OK;
+}
+
+pd_status pd_set_pipeline(pd_ctx* c, int chunks, int speculate_all) {
+  if (!c) return PD_EINVAL;
+  if (chunks < 0 || chunks > 64) return fail(c, PD_EINVAL, "chunks must be in [0, 64]");
+  c->pipe_chunks = chunks;
+  c->pipe_spec = speculate_all != 0;
   return PD_OK;
 }
 
@@ -399,6 +412,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   if (kres >= 0 && max_iter <= kres)
     return fail(c, PD_EINVAL, "max_iter must exceed the resumed iteration %d", kres);
   c->resume_k = -1;
+  if (!learned && c->pipe_chunks > 1) return parareal_pipelined(c, tol, max_iter, kres, rep);
   pd_report r;
   std::memset(&r, 0, sizeof r);
   r.k_con = -1;

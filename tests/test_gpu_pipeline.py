@@ -1,0 +1,61 @@
+"""GPU tests of pipelined Parareal: the overlapped schedule (coarse sweep on
+its own stream in runs of slices, fine sweeps of the next iteration started
+early) gives bitwise the iterates, defects and k_con of the plain order."""
+import numpy as np
+import pytest
+
+from synthetic import initial_field
+
+pytestmark = pytest.mark.gpu
+
+
+def run(lib, chunks, P=10, N=32, tol=1e-10, max_iter=None, flow="gp", Nc=16, resume=None, form=0,
+        spec=True):
+    with lib.Context(0) as ctx:
+        ctx.set_problem(flow, 60.0, 0.57, N)
+        ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, Nc)
+        ctx.set_coarse_form(form)
+        ctx.set_pipeline(chunks, spec)
+        b0 = initial_field(N, 0.57, 77)
+        if resume is None:
+            ctx.set_initial(b0)
+        else:
+            ctx.set_initial(b0)
+            ctx.set_pipeline(0)
+            ctx.parareal(0.0, resume)
+            U, G = ctx.get_slices(), ctx.get_coarse_values()
+            ctx.set_pipeline(chunks, spec)
+            ctx.set_slices(U, G, resume)
+        rep = ctx.parareal(tol, P + 1 if max_iter is None else max_iter)
+        return rep, ctx.get_slices(), ctx.get_coarse_values()
+
+
+@pytest.mark.parametrize("chunks,spec", [(2, True), (3, True), (4, False), (7, True), (10, False),
+                                         (64, True)])
+def test_pipelined_equals_plain_order_bitwise(lib, chunks, spec):
+    r0, U0, G0 = run(lib, 0)
+    r1, U1, G1 = run(lib, chunks, spec=spec)
+    assert r0["k_con"] == r1["k_con"] and r0["iters"] == r1["iters"]
+    assert r0["sigma"][:r0["iters"]] == r1["sigma"][:r1["iters"]]
+    assert np.array_equal(U0, U1)
+    assert np.array_equal(G0, G1)
+
+
+def test_pipelined_fixed_iterations_and_no_iterations(lib):
+    for it in (0, 1, 3):
+        r0, U0, _ = run(lib, 0, tol=0.0, max_iter=it)
+        r1, U1, _ = run(lib, 4, tol=0.0, max_iter=it)
+        assert r0["iters"] == r1["iters"] == it
+        assert np.array_equal(U0, U1)
+
+
+def test_pipelined_resume_and_fft_coarse_form(lib):
+    r0, U0, _ = run(lib, 0, resume=2)
+    r1, U1, _ = run(lib, 3, resume=2)
+    assert r0["k_con"] == r1["k_con"]
+    assert np.array_equal(U0, U1)
+    # the pseudo-spectral (FFT) form of the coarse sweep
+    r0, U0, _ = run(lib, 0, P=6, tol=1e-8, form=1)
+    r1, U1, _ = run(lib, 4, P=6, tol=1e-8, form=1)
+    assert r0["k_con"] == r1["k_con"] > 0
+    assert np.array_equal(U0, U1)
