@@ -71,14 +71,18 @@ def cpu_baseline(budget_s=15.0):
                       f"(serial, {dt:.1f} s)"}
 
 
-KERNELS_SRC = os.path.join(ROOT, "paper_1902_00387_amd", "csrc", "kernels.hip")
+KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "launch.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gp128_p64.json")
 
 
 def kernels_digest():
+    """Digest of the fine-step kernel sources (counters go stale when they change)."""
     import hashlib
-    with open(KERNELS_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1902_00387_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def summarize_pmc(fetch_csv, write_csv, out_path):
