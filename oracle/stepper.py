@@ -1,4 +1,4 @@
-"""IMEX multistep slice propagators and Fourier resampling (oracle).
+"""IMEX slice propagators (SBDF2, ARS(4,4,3)) and Fourier resampling (oracle).
 
 TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 
@@ -47,6 +47,70 @@ def propagate(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
     return b
 
 
+# ARS(4,4,3): the four-stage, third-order, L-stable and stiffly accurate IMEX
+# Runge-Kutta pair of Ascher, Ruuth & Spiteri (1997), the "RK443" the paper
+# steps with (Section 4; Section 5.1 compares it with lower-order pairs).
+# Stage i (i = 1..5, stage 1 = the step's start value) solves
+#   X_i = b_n + dt sum_{j<i} A_ij N(X_j, t + C_j dt) + dt sum_{j<=i} AT_ij L X_j,
+# L = -|k|^2/Rm diagonal, and both parts are stiffly accurate: b_{n+1} = X_5.
+from fractions import Fraction as _Fr
+
+RK443_C = (_Fr(0), _Fr(1, 2), _Fr(2, 3), _Fr(1, 2), _Fr(1))
+RK443_A = (  # explicit part, strictly lower triangular
+    (),
+    (_Fr(1, 2),),
+    (_Fr(11, 18), _Fr(1, 18)),
+    (_Fr(5, 6), _Fr(-5, 6), _Fr(1, 2)),
+    (_Fr(1, 4), _Fr(7, 4), _Fr(3, 4), _Fr(-7, 4)),
+)
+RK443_AT = (  # implicit part, lower triangular with diagonal 1/2 (first row and column zero)
+    (_Fr(0),),
+    (_Fr(0), _Fr(1, 2)),
+    (_Fr(0), _Fr(1, 6), _Fr(1, 2)),
+    (_Fr(0), _Fr(-1, 2), _Fr(1, 2), _Fr(1, 2)),
+    (_Fr(0), _Fr(3, 2), _Fr(-3, 2), _Fr(1, 2), _Fr(1, 2)),
+)
+
+
+def propagate_rk443(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
+                    dt: float, nsteps: int) -> np.ndarray:
+    """Advance one field ``[3][N][N]`` by ``nsteps`` ARS(4,4,3) steps of size
+    ``dt`` from time ``t0`` (step j starts at t0 + j dt, a product; stage i
+    of it evaluates the flow at t0 + j dt + C_i dt).  A one-step method, so
+    nothing restarts at slice boundaries."""
+    if nsteps < 1:
+        raise ValueError("nsteps must be >= 1")
+    N = bh.shape[-1]
+    L = -sp.k_squared(N, kz) / Rm
+    A = [[float(v) for v in row] for row in RK443_A]
+    AT = [[float(v) for v in row] for row in RK443_AT]
+    C = [float(v) for v in RK443_C]
+    b = np.array(bh, dtype=np.complex128)
+    for j in range(nsteps):
+        t = t0 + j * dt
+        X, NX = [], []
+        for i in range(5):
+            rhs = b.copy()
+            for m in range(i):
+                rhs = rhs + dt * (A[i][m] * NX[m] + AT[i][m] * L * X[m])
+            Xi = rhs / (1.0 - dt * AT[i][i] * L) if AT[i][i] != 0.0 else rhs
+            X.append(Xi)
+            if i < 4:
+                NX.append(sp.explicit_term(Xi, flow, kz, t + C[i] * dt))
+        b = X[4]
+    return b
+
+
+def propagate_scheme(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
+                     dt: float, nsteps: int, scheme: str = "sbdf2") -> np.ndarray:
+    """``propagate`` (scheme "sbdf2") or ``propagate_rk443`` ("rk443")."""
+    if scheme == "sbdf2":
+        return propagate(bh, flow, Rm, kz, t0, dt, nsteps)
+    if scheme == "rk443":
+        return propagate_rk443(bh, flow, Rm, kz, t0, dt, nsteps)
+    raise ValueError(f"unknown scheme {scheme!r}")
+
+
 def restrict(bh: np.ndarray, Nc: int) -> np.ndarray:
     """Fine ``[3][N][N]`` -> coarse ``[3][Nc][Nc]``: keep the modes with
     |kx|, |ky| <= floor((Nc - 1)/3), drop the rest."""
@@ -88,7 +152,7 @@ class SliceSolver:
     """
 
     def __init__(self, flow: str, Rm: float, kz: float, N: int, dT: float,
-                 dt: float, N_solver: int | None = None):
+                 dt: float, N_solver: int | None = None, scheme: str = "sbdf2"):
         steps = dT / dt
         n = int(round(steps))
         if n < 1 or abs(steps - n) > 1e-9 * max(1.0, steps):
@@ -96,8 +160,10 @@ class SliceSolver:
         self.flow, self.Rm, self.kz, self.N = flow, Rm, kz, N
         self.dT, self.dt, self.nsteps = dT, dt, n
         self.N_solver = N if N_solver is None else N_solver
+        self.scheme = scheme
 
     def __call__(self, bh: np.ndarray, t0: float) -> np.ndarray:
         x = restrict(bh, self.N_solver)
-        y = propagate(x, self.flow, self.Rm, self.kz, t0, self.dt, self.nsteps)
+        y = propagate_scheme(x, self.flow, self.Rm, self.kz, t0, self.dt, self.nsteps,
+                             self.scheme)
         return prolong(y, self.N)

@@ -101,3 +101,73 @@ def test_restrict_prolong_roundtrip_and_interpolation():
 def test_slice_solver_rejects_non_integer_step_count():
     with pytest.raises(ValueError):
         stepper.SliceSolver("gp", 10.0, 1.0, 16, 1.0, 0.3)
+
+
+# ---- ARS(4,4,3) ------------------------------------------------------------
+
+def test_rk443_tableau_order_conditions():
+    """Both parts of the transcribed ARS(4,4,3) tableau satisfy the Runge-Kutta
+    order conditions up to order 3 and the two coupling conditions of an
+    order-3 IMEX pair (exact rational arithmetic); row sums equal the stage
+    times; both parts are stiffly accurate."""
+    from fractions import Fraction as Fr
+    C = stepper.RK443_C
+    A = [list(r) + [Fr(0)] * (5 - len(r)) for r in stepper.RK443_A]
+    AT = [list(r) + [Fr(0)] * (5 - len(r)) for r in stepper.RK443_AT]
+    b, bt = A[4], AT[4]  # stiffly accurate: the weights are the last rows
+    assert b[4] == 0 and bt[4] == Fr(1, 2)
+    for i in range(5):
+        assert sum(A[i]) == C[i] and sum(AT[i]) == C[i]
+        assert all(A[i][j] == 0 for j in range(i, 5))
+        assert all(AT[i][j] == 0 for j in range(i + 1, 5))
+        assert AT[i][0] == 0 and (i == 0 or AT[i][i] == Fr(1, 2))
+    for w, M in ((b, A), (bt, AT)):
+        assert sum(w) == 1
+        assert sum(w[i] * C[i] for i in range(5)) == Fr(1, 2)
+        assert sum(w[i] * C[i] ** 2 for i in range(5)) == Fr(1, 3)
+        assert sum(w[i] * M[i][j] * C[j] for i in range(5) for j in range(5)) == Fr(1, 6)
+    # coupling of the explicit and implicit parts
+    assert sum(b[i] * AT[i][j] * C[j] for i in range(5) for j in range(5)) == Fr(1, 6)
+    assert sum(bt[i] * A[i][j] * C[j] for i in range(5) for j in range(5)) == Fr(1, 6)
+
+
+def test_rk443_pure_diffusion_third_order_and_l_stable():
+    """u = 0 against exp(-|k|^2 t/Rm): error ~ dt^3; one huge step (|k|^2 dt/Rm
+    ~ 1e6) damps every mode to nearly zero (L-stability)."""
+    N, kz, Rm, T = 16, 1.0, 5.0, 1.0
+    b0 = initial_field(N, kz, 3)
+    exact = b0 * np.exp(-sp.k_squared(N, kz) * T / Rm)[None]
+    errs = []
+    for n in (10, 20, 40):
+        b = stepper.propagate_rk443(b0, "none", Rm, kz, 0.0, T / n, n)
+        errs.append(np.linalg.norm(b - exact) / np.linalg.norm(exact))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 6.5 < r1 < 9.5 and 6.5 < r2 < 9.5, errs
+    big = stepper.propagate_rk443(b0, "none", 1e-6, kz, 0.0, 1.0, 1)
+    assert np.linalg.norm(big) <= 1e-5 * np.linalg.norm(b0)
+
+
+def test_rk443_gp_trajectory_third_order_against_independent_integrator():
+    """The ARS(4,4,3) solution of the Galloway-Proctor dynamo over [0.4, 2.4]
+    against DOP853 on the direct-convolution ODE: error ratio near 8 when dt
+    halves."""
+    N, kz, Rm = 16, 0.57, 3.0
+    b0 = initial_field(N, kz, 5, amp=1.0)
+    t0, T = 0.4, 2.0
+    ref = solve_ivp(_direct_rhs("gp", Rm, kz, N), (t0, t0 + T), b0.ravel(),
+                    method="DOP853", rtol=1e-12, atol=1e-14).y[:, -1].reshape(b0.shape)
+    errs = []
+    for dt in (4e-2, 2e-2, 1e-2):
+        got = stepper.propagate_rk443(b0, "gp", Rm, kz, t0, dt, int(round(T / dt)))
+        errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    assert errs[2] < 1e-5, errs
+    assert 6.0 < errs[0] / errs[1] < 10.0 and 6.0 < errs[1] / errs[2] < 10.0, errs
+
+
+def test_rk443_slice_solver_and_scheme_switch():
+    N, kz = 16, 0.57
+    b0 = initial_field(N, kz, 6)
+    F = stepper.SliceSolver("roberts", 10.0, kz, N, 0.5, 0.05, scheme="rk443")
+    assert np.array_equal(F(b0, 0.0), stepper.propagate_rk443(b0, "roberts", 10.0, kz, 0.0, 0.05, 10))
+    with pytest.raises(ValueError):
+        stepper.propagate_scheme(b0, "roberts", 10.0, kz, 0.0, 0.05, 1, "rk4")
