@@ -83,6 +83,14 @@ typedef enum {
                           aliases on the 2/3 box; N_coarse <= 64             */
 } pd_coarse_form;
 
+/* Time steppers (Section 4: IMEX, explicit advection and stretching, implicit
+   diffusion).  Both restart from the slice's start value in every slice. */
+typedef enum {
+  PD_SCHEME_SBDF2 = 0,  /* one SBDF1 step, then SBDF2 (multistep, restarted) */
+  PD_SCHEME_RK443 = 1   /* ARS(4,4,3) IMEX Runge-Kutta, the paper's RK443:
+                           four explicit evaluations a step */
+} pd_scheme;
+
 #define PD_MAX_ITER 256
 
 typedef struct {
@@ -122,6 +130,12 @@ pd_status pd_set_path(pd_ctx* ctx, pd_path path);
 /* Choose how pd_parareal's serial coarse sweep evaluates the explicit term
    (one workgroup runs the whole sweep either way). */
 pd_status pd_set_coarse_form(pd_ctx* ctx, pd_coarse_form form);
+/* Steppers of the fine and the coarse propagator (default SBDF2 for both;
+   applies to pd_fine_dev / pd_coarse_dev / pd_steps_dev / pd_step_* and
+   pd_parareal).  The convolution form of the coarse sweep steps SBDF2 only,
+   so a Runge-Kutta coarse propagator runs the FFT form (PD_EINVAL together
+   with PD_COARSE_CONV).  Batched instances (pd_batch_*) step SBDF2. */
+pd_status pd_set_scheme(pd_ctx* ctx, pd_scheme fine, pd_scheme coarse);
 
 /* Initial field U_0, full layout [3][N][N], host or device memory. */
 pd_status pd_set_initial(pd_ctx* ctx, const double* b0);

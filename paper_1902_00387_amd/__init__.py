@@ -43,7 +43,7 @@ SYMBOLS = [
     "pd_lg_init", "pd_lg_add_samples", "pd_lg_add_parareal_samples", "pd_lg_train", "pd_lg_loss", "pd_lg_gradients",
     "pd_lg_params", "pd_lg_set_params", "pd_lg_sample", "pd_lg_forward_sample", "pd_set_coarse",
     "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
-    "pd_lg_load", "pd_set_pipeline",
+    "pd_lg_load", "pd_set_pipeline", "pd_set_scheme",
 ]
 
 
@@ -130,6 +130,7 @@ def _load():
         "pd_lg_save": ([vp, C.c_char_p], i),
         "pd_lg_load": ([vp, C.c_char_p], i),
         "pd_set_pipeline": ([vp, i, i], i),
+        "pd_set_scheme": ([vp, i, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -247,7 +248,7 @@ class Context:
         return self._prop(lib.pd_coarse_dev, t0, x, out)
 
     def steps(self, t0, dt: float, n_steps: int, x, out=None):
-        """n_steps SBDF steps of size dt on the fine grid."""
+        """n_steps steps of the fine scheme with size dt on the fine grid."""
         return self._prop(lib.pd_steps_dev, t0, x, out, C.c_double(dt), C.c_int(n_steps))
 
     # -- Parareal -----------------------------------------------------------
@@ -268,6 +269,11 @@ class Context:
         self._ok(fn(self._h, _dptr(t), bb.shape[0], _dptr(bb.view(np.float64)),
                     _dptr(out.view(np.float64))))
         return out
+
+    def set_scheme(self, fine: str = "sbdf2", coarse: str = "sbdf2"):
+        """Time steppers of F and G: "sbdf2" or "rk443" (ARS(4,4,3))."""
+        code = {"sbdf2": 0, "rk443": 1}
+        self._ok(lib.pd_set_scheme(self._h, code[fine], code[coarse]))
 
     def set_pipeline(self, chunks: int, speculate_all: bool = True):
         """Pipelined Parareal over `chunks` runs of slices (0 or 1: off)."""

@@ -26,6 +26,8 @@ struct pd_ctx {
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;
+  int scheme_f = PD_SCHEME_SBDF2;  // time steppers of F and G
+  int scheme_c = PD_SCHEME_SBDF2;
   // problem
   bool have_problem = false;
   int flow = PD_FLOW_NONE;
@@ -45,6 +47,7 @@ struct pd_ctx {
   DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
   DevBuf red, flag;                    // reduction outputs, box-check flag
   DevBuf ftab;                         // flow phases at every coarse step time
+  DevBuf Rf, Rc, wR;                   // Runge-Kutta stage sums: slices, coarse sweep, propagator calls
   DevBuf wB, wH, wT1, wT2, wt0;        // workspaces of the propagator calls
   double* hred = nullptr;              // pinned host copy of red
   // learned coarse propagator (correction network) state
@@ -87,14 +90,15 @@ struct DeviceGuard {
   }
 };
 
-pd::Problem make_problem(const pd_ctx* c, double dt);
+pd::Problem make_problem(const pd_ctx* c, double dt, int scheme = PD_SCHEME_SBDF2);
+pd_status ensure_rk_buffers(pd_ctx* c);
 bool use_conv_sweep(const pd_ctx* c);
 int choose_path(const pd_ctx* c, int nfields);
 hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
                       int nsteps, hipStream_t st);
 pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStream_t st);
 pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
-                         int Ngrid, const void* d_in, void* d_out, hipStream_t st);
+                         int Ngrid, const void* d_in, void* d_out, hipStream_t st, int scheme);
 // learned coarse propagator (lg.cpp)
 void lg_release(pd_ctx* c);
 pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st);

@@ -28,8 +28,10 @@ pd_status step_host(pd_ctx* c, const double* t0, int batch, const double* in, do
   DevBuf d;
   PD_HIP(c, d.ensure(bytes), "alloc");
   PD_HIP(c, hipMemcpyAsync(d.p, in, bytes, hipMemcpyHostToDevice, c->stream), "copy");
-  pd_status s = fine ? run_propagator(c, t0, batch, c->dtf, c->nf, c->N, d.p, d.p, c->stream)
-                     : run_propagator(c, t0, batch, c->dtc, c->nc, c->Nc, d.p, d.p, c->stream);
+  pd_status s = fine ? run_propagator(c, t0, batch, c->dtf, c->nf, c->N, d.p, d.p, c->stream,
+                                      c->scheme_f)
+                     : run_propagator(c, t0, batch, c->dtc, c->nc, c->Nc, d.p, d.p, c->stream,
+                                      c->scheme_c);
   if (s != PD_OK) return s;
   PD_HIP(c, hipMemcpyAsync(out, d.p, bytes, hipMemcpyDeviceToHost, c->stream), "copy");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");

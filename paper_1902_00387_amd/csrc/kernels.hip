@@ -18,6 +18,8 @@
 //   row phase (T2 -> B, H, T1): forward x-FFT of each box row, keep the box
 //     columns, scale 1/N^2, spectral curl i k x E, SBDF update with the
 //     diagonal implicit diffusion solve, inverse x-FFT of the new row.
+#include <type_traits>
+
 #include "fft.hpp"
 #include "launch.hpp"
 
@@ -71,15 +73,64 @@ __device__ __forceinline__ FlowPhase flow_phase(const Problem& pb, double t) {
 }
 
 // ---------------------------------------------------------------------------
+// ARS(4,4,3) (Ascher, Ruuth & Spiteri 1997; the paper's RK443, Section 4):
+// stage i = 1..5 has time t + c_i dt and solves
+//   X_i = b_n + dt sum_{j<i} (a_ij N(X_j) + at_ij L X_j) + dt at_ii L X_i,
+// L = -|k|^2/Rm, at_ii = 1/2 for i >= 2; both parts are stiffly accurate,
+// so b_{n+1} = X_5.  The stage sums R_i (i = 2..5) collect the j < i terms
+// as the stages go; X_i = R_i / (1 - dt L / 2).
+__host__ __device__ constexpr double ars_c(int i) {
+  return i == 1 ? 0.0 : i == 2 ? 0.5 : i == 3 ? 2.0 / 3.0 : i == 4 ? 0.5 : 1.0;
+}
+__host__ __device__ constexpr double ars_a(int i, int j) {  // explicit part, j < i
+  return i == 2 ? (j == 1 ? 0.5 : 0.0)
+       : i == 3 ? (j == 1 ? 11.0 / 18.0 : j == 2 ? 1.0 / 18.0 : 0.0)
+       : i == 4 ? (j == 1 ? 5.0 / 6.0 : j == 2 ? -5.0 / 6.0 : j == 3 ? 0.5 : 0.0)
+       : i == 5 ? (j == 1 ? 0.25 : j == 2 ? 1.75 : j == 3 ? 0.75 : j == 4 ? -1.75 : 0.0)
+                : 0.0;
+}
+__host__ __device__ constexpr double ars_at(int i, int j) {  // implicit part, j < i
+  return i == 3 ? (j == 2 ? 1.0 / 6.0 : 0.0)
+       : i == 4 ? (j == 2 ? -0.5 : j == 3 ? 0.5 : 0.0)
+       : i == 5 ? (j == 2 ? 1.5 : j == 3 ? -1.5 : j == 4 ? 0.5 : 0.0)
+                : 0.0;
+}
+
+__device__ __forceinline__ cplx cdivr(cplx a, double d) { return {a.re / d, a.im / d}; }
+
+// End of stage JS (1..4) for one mode of one component: X_JS from the
+// state (JS = 1) or its stage sum, the contributions of stage JS to the
+// later stage sums, and X_{JS+1}; after stage 4, X_5 is the new state.
+template <int JS>
+__device__ __forceinline__ cplx rk_update(cplx nl, double L, double d, double dt, size_t idx,
+                                          size_t rs, cplx* __restrict__ B, cplx* __restrict__ R) {
+  const cplx X = JS == 1 ? B[idx] : cdivr(R[(JS - 2) * rs + idx], d);
+  cplx next = czero();
+#pragma unroll
+  for (int i = JS + 1; i <= 5; ++i) {
+    const double a = ars_a(i, JS), atl = ars_at(i, JS) * L;
+    const cplx base = JS == 1 ? X : R[(i - 2) * rs + idx];
+    const cplx term = {a * nl.re + atl * X.re, a * nl.im + atl * X.im};
+    const cplx Ri = cadd(base, cscale(term, dt));
+    if (i == JS + 1) next = cdivr(Ri, d);
+    if (i == 5 && JS == 4) B[idx] = next;
+    else R[(i - 2) * rs + idx] = Ri;
+  }
+  return next;
+}
+
+// ---------------------------------------------------------------------------
 // Row phase of one box row r of one field, by one group of T lanes (lane j)
 // inside a wavefront; no workgroup barrier.
 // mode 0: start of a slice (inverse transform of the state only);
-// mode 1: SBDF1 update; mode 2: SBDF2 update.  last: skip the inverse.
-template <int N, int E>
+// mode 1: SBDF1 update; mode 2: SBDF2 update; RKS = j > 0 (mode ROW_RK + j):
+// end of ARS(4,4,3) stage j (stage sums in R).  last: skip the inverse.
+template <int N, int E, int RKS = 0>
 __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cplx* __restrict__ B,
                                           cplx* __restrict__ H, const cplx* __restrict__ T2,
                                           cplx* __restrict__ T1, const cplx* __restrict__ tw,
-                                          const Problem& pb, int mode, bool last) {
+                                          const Problem& pb, int mode, bool last,
+                                          cplx* __restrict__ R = nullptr) {
   using G = Geo<N, E>;
   constexpr int T = G::T, K = G::K, M = G::M;
   TwRegs<N, E> twr;
@@ -115,23 +166,34 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
         nl[0] = mul_i<1>(csub(cscale(ez, dky), cscale(ey, kz)));
         nl[1] = mul_i<1>(csub(cscale(ex, kz), cscale(ez, dkx)));
         nl[2] = mul_i<1>(csub(cscale(ey, dkx), cscale(ex, dky)));
-        const double a = dt * (dkx * dkx + dky * dky + kz * kz) / pb.Rm;
+        if constexpr (RKS > 0) {
+          const double L = -(dkx * dkx + dky * dky + kz * kz) / pb.Rm;
+          const double d = 1.0 - dt * 0.5 * L;
+          const size_t rs = (size_t)3 * M * M;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int idx = (c * M + r) * M + kx + K;
-          const cplx b = B[idx];
-          cplx bn;
-          if (mode == 1) {
-            const double inv = 1.0 / (1.0 + a);
-            bn = cscale(cadd(b, cscale(nl[c], dt)), inv);
-          } else {
-            const double inv = 1.0 / (1.5 + a);
-            const cplx h = H[idx];
-            bn = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), h), inv);
+          for (int c = 0; c < 3; ++c) {
+            const size_t idx = (size_t)(c * M + r) * M + kx + K;
+            w[c][e] = rk_update<RKS>(nl[c], L, d, dt, idx, rs, B, R);
           }
-          H[idx] = csub(cscale(b, -0.5), cscale(nl[c], dt));
-          B[idx] = bn;
-          w[c][e] = bn;
+        } else {
+          const double a = dt * (dkx * dkx + dky * dky + kz * kz) / pb.Rm;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int idx = (c * M + r) * M + kx + K;
+            const cplx b = B[idx];
+            cplx bn;
+            if (mode == 1) {
+              const double inv = 1.0 / (1.0 + a);
+              bn = cscale(cadd(b, cscale(nl[c], dt)), inv);
+            } else {
+              const double inv = 1.0 / (1.5 + a);
+              const cplx h = H[idx];
+              bn = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), h), inv);
+            }
+            H[idx] = csub(cscale(b, -0.5), cscale(nl[c], dt));
+            B[idx] = bn;
+            w[c][e] = bn;
+          }
         }
       } else {
 #pragma unroll
@@ -278,7 +340,7 @@ __host__ __device__ constexpr int tile_elems(int lanes) {
 
 // ---------------------------------------------------------------------------
 // Multi-launch path: one launch per phase over every (field, tile).
-template <int N, int E, int W>
+template <int N, int E, int W, int RKS>
 __global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int mode, int last) {
   using G = Geo<N, E>;
   constexpr int RPW = W * 64 / G::T;
@@ -291,19 +353,24 @@ __global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int 
   Problem p = pb;
   if (fb.fRm != nullptr) p.Rm = fb.fRm[f];
   if (fb.fkz != nullptr) p.kz = fb.fkz[f];
-  row_phase<N, E>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
-                  fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, p, mode, last != 0);
+  row_phase<N, E, RKS>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
+                       fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, p, mode, last != 0,
+                       RKS > 0 ? fb.R + 4 * f * box : nullptr);
 }
 
 template <int N, int E, int TX, int MINW>
 __global__ __launch_bounds__(TX * (N / E))
-__attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb, int step) {
+__attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb, int step,
+                                                        int stage) {
   using G = Geo<N, E>;
   __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
   if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
   const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
   const size_t rows = (size_t)3 * G::M * N;
-  const FlowPhase fp = flow_phase(pb, fb.t0[f] + step * pb.dt);
+  // SBDF steps at t0 + step dt; Runge-Kutta stage `stage` at t0 + step dt + c dt
+  const double t = stage == 0 ? fb.t0[f] + step * pb.dt
+                              : fb.t0[f] + step * pb.dt + ars_c(stage) * pb.dt;
+  const FlowPhase fp = flow_phase(pb, t);
   col_tile<N, E, TX * G::T, E == 8 ? 8 : 4>(blockIdx.x * TX, tile, fb.T1 + f * rows,
                                             fb.T2 + f * rows, fb.tw, fp);
 }
@@ -325,10 +392,10 @@ struct SingleLds {
   static constexpr int LDS = TILE > SPANS ? TILE : SPANS;
 };
 
-template <int N>
+template <int N, bool RK>
 __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* T1,
                                              cplx* T2, const cplx* tw, const Problem& pb,
-                                             double t0, int nsteps) {
+                                             double t0, int nsteps, cplx* R) {
   using S = SingleLds<N>;
   constexpr int ER = Shape<N>::ESR, EC = Shape<N>::ESC;
   constexpr int TR = S::GR::T, M = S::GR::M, NGR = S::NGR, NGC = S::NGC;
@@ -341,19 +408,38 @@ __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* 
     row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb, 0,
                      false);
   __syncthreads();
-  for (int step = 0; step < nsteps; ++step) {
-    const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
-    for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
-    const int mode = step == 0 ? 1 : 2;
-    const bool last = step == nsteps - 1;
-    for (int r0 = 0; r0 < M; r0 += NGR)
-      row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb,
-                       mode, last);
-    __syncthreads();
+  if constexpr (RK) {  // ARS(4,4,3): four stages a step
+    for (int step = 0; step < nsteps; ++step) {
+      auto stage = [&](auto js_c) {
+        constexpr int js = decltype(js_c)::value;
+        const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt + ars_c(js) * pb.dt);
+        for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
+        const bool last = step == nsteps - 1 && js == 4;
+        for (int r0 = 0; r0 < M; r0 += NGR)
+          row_phase<N, ER, js>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1,
+                               tw, pb, ROW_RK + js, last, R);
+        __syncthreads();
+      };
+      stage(std::integral_constant<int, 1>{});
+      stage(std::integral_constant<int, 2>{});
+      stage(std::integral_constant<int, 3>{});
+      stage(std::integral_constant<int, 4>{});
+    }
+  } else {
+    for (int step = 0; step < nsteps; ++step) {
+      const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
+      for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
+      const int mode = step == 0 ? 1 : 2;
+      const bool last = step == nsteps - 1;
+      for (int r0 = 0; r0 < M; r0 += NGR)
+        row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb,
+                         mode, last);
+      __syncthreads();
+    }
   }
 }
 
-template <int N>
+template <int N, bool RK>
 __global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Problem pb, int nsteps) {
   using S = SingleLds<N>;
   __shared__ cplx lds[S::LDS];
@@ -363,8 +449,8 @@ __global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Proble
   Problem p = pb;
   if (fb.fRm != nullptr) p.Rm = fb.fRm[f];
   if (fb.fkz != nullptr) p.kz = fb.fkz[f];
-  propagate_wg<N>(lds, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows,
-                  fb.tw, p, fb.t0[f], nsteps);
+  propagate_wg<N, RK>(lds, fb.B + f * box, fb.H + f * box, fb.T1 + f * rows, fb.T2 + f * rows,
+                      fb.tw, p, fb.t0[f], nsteps, RK ? fb.R + 4 * f * box : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,7 +463,7 @@ __global__ __launch_bounds__(Shape<N>::LANES) void k_slice(FieldBatch fb, Proble
 // [3][Mc][Mc] block, so restriction and zero-padding prolongation are index
 // maps.  After the last slice the defect sums |U_P - Uprev_P|^2 and |U_P|^2
 // are reduced in a fixed order into red[0], red[1].
-template <int NC>
+template <int NC, bool RK>
 __global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem pb) {
   using S = SingleLds<NC>;
   __shared__ cplx lds[S::LDS];
@@ -393,7 +479,8 @@ __global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem
       a.Bc[i] = Un[(c * M + rr + K - Kc) * M + cc + K - Kc];
     }
     __syncthreads();
-    propagate_wg<NC>(lds, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, (a.nbase + n) * a.dT, a.nsteps);
+    propagate_wg<NC, RK>(lds, a.Bc, a.Hc, a.T1c, a.T2c, a.twc, pb, (a.nbase + n) * a.dT,
+                         a.nsteps, a.Rc);
     cplx* Un1 = a.U + (n + 1) * fbox;
     cplx* Go = a.Gold + n * fbox;
     const cplx* Fn = a.Fo + n * fbox;
@@ -888,22 +975,30 @@ static hipError_t launch_rows_v(const FieldBatch& fb, const Problem& pb, int nfi
   using G = Geo<N, E>;
   constexpr int RPW = W * 64 / G::T;
   dim3 grid((G::M + RPW - 1) / RPW, nfields);
-  hipLaunchKernelGGL((k_rows<N, E, W>), grid, dim3(64 * W), 0, st, fb, pb, mode, last);
+  // each Runge-Kutta stage (mode ROW_RK + j) runs its own instantiation, so
+  // the SBDF kernels keep their register budget
+  switch (mode - ROW_RK) {
+    case 1: hipLaunchKernelGGL((k_rows<N, E, W, 1>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
+    case 2: hipLaunchKernelGGL((k_rows<N, E, W, 2>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
+    case 3: hipLaunchKernelGGL((k_rows<N, E, W, 3>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
+    case 4: hipLaunchKernelGGL((k_rows<N, E, W, 4>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
+    default: hipLaunchKernelGGL((k_rows<N, E, W, 0>), grid, dim3(64 * W), 0, st, fb, pb, mode, last);
+  }
   return hipGetLastError();
 }
 
 template <int N, int E, int TX, int MINW>
 static hipError_t launch_cols_v(const FieldBatch& fb, const Problem& pb, int nfields, int step,
-                                hipStream_t st) {
+                                int stage, hipStream_t st) {
   constexpr int T = N / E;
   dim3 grid((N + TX - 1) / TX, nfields);
-  hipLaunchKernelGGL((k_cols<N, E, TX, MINW>), grid, dim3(TX * T), 0, st, fb, pb, step);
+  hipLaunchKernelGGL((k_cols<N, E, TX, MINW>), grid, dim3(TX * T), 0, st, fb, pb, step, stage);
   return hipGetLastError();
 }
 
 // ---- launch-shape variants and the per-size choice (autotuned) -----------
 using RowsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, int, hipStream_t);
-using ColsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, hipStream_t);
+using ColsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, int, hipStream_t);
 struct RowsVariant {
   int E, W;
   RowsFn fn;
@@ -991,8 +1086,8 @@ static hipError_t launch_rows(const FieldBatch& fb, const Problem& pb, int nfiel
 
 template <int N>
 static hipError_t launch_cols(const FieldBatch& fb, const Problem& pb, int nfields, int step,
-                              hipStream_t st) {
-  return Variants<N>::cols[g_cols_choice[size_slot(N)]].fn(fb, pb, nfields, step, st);
+                              hipStream_t st, int stage = 0) {
+  return Variants<N>::cols[g_cols_choice[size_slot(N)]].fn(fb, pb, nfields, step, stage, st);
 }
 
 template <int N>
@@ -1057,7 +1152,12 @@ void variant_current(int N, int* rows_v, int* cols_v) {
 template <int N>
 static hipError_t launch_slice(const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_slice<N>, dim3(nfields), dim3(Shape<N>::LANES), 0, st, fb, pb, nsteps);
+  if (pb.scheme == 1)
+    hipLaunchKernelGGL((k_slice<N, true>), dim3(nfields), dim3(Shape<N>::LANES), 0, st, fb, pb,
+                       nsteps);
+  else
+    hipLaunchKernelGGL((k_slice<N, false>), dim3(nfields), dim3(Shape<N>::LANES), 0, st, fb, pb,
+                       nsteps);
   return hipGetLastError();
 }
 
@@ -1065,6 +1165,15 @@ template <int N>
 static hipError_t propagate_multi(const FieldBatch& fb, const Problem& pb, int nfields,
                                   int nsteps, hipStream_t st) {
   hipError_t e = launch_rows<N>(fb, pb, nfields, 0, 0, st);
+  if (pb.scheme == 1) {  // ARS(4,4,3): one column and one row launch a stage
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s)
+      for (int j = 1; j <= 4 && e == hipSuccess; ++j) {
+        e = launch_cols<N>(fb, pb, nfields, s, st, j);
+        if (e == hipSuccess)
+          e = launch_rows<N>(fb, pb, nfields, ROW_RK + j, s == nsteps - 1 && j == 4, st);
+      }
+    return e;
+  }
   for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
     e = launch_cols<N>(fb, pb, nfields, s, st);
     if (e == hipSuccess) e = launch_rows<N>(fb, pb, nfields, s == 0 ? 1 : 2, s == nsteps - 1, st);
@@ -1108,7 +1217,7 @@ static hipError_t propagate_multi2(const FieldBatch& fb, const Problem& pb, int 
 hipError_t propagate2(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                       hipStream_t st, hipStream_t st2, hipEvent_t* ev) {
   if (nfields <= 0 || nsteps <= 0) return hipSuccess;
-  if (nfields < 2) return propagate(N, fb, pb, nfields, nsteps, PATH_MULTI, st);
+  if (nfields < 2 || pb.scheme != 0) return propagate(N, fb, pb, nfields, nsteps, PATH_MULTI, st);
   switch (N) {
     case 16: return propagate_multi2<16>(fb, pb, nfields, nsteps, st, st2, ev);
     case 32: return propagate_multi2<32>(fb, pb, nfields, nsteps, st, st2, ev);
@@ -1123,6 +1232,7 @@ hipError_t propagate2(int N, const FieldBatch& fb, const Problem& pb, int nfield
 hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                      int path, hipStream_t st) {
   if (nfields <= 0 || nsteps <= 0) return hipSuccess;
+  if (pb.scheme == 1 && fb.R == nullptr) return hipErrorInvalidValue;  // stage sums needed
   if (path == PATH_SINGLE_WG) {
 #define CALL(n) launch_slice<n>(fb, pb, nfields, nsteps, st)
     switch (N) {
@@ -1177,13 +1287,16 @@ hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int
 
 template <int NC>
 static hipError_t launch_sweep(const SweepArgs& a, const Problem& pb, hipStream_t st) {
-  hipLaunchKernelGGL(k_sweep<NC>, dim3(1), dim3(Shape<NC>::LANES), 0, st, a, pb);
+  if (pb.scheme == 1)
+    hipLaunchKernelGGL((k_sweep<NC, true>), dim3(1), dim3(Shape<NC>::LANES), 0, st, a, pb);
+  else
+    hipLaunchKernelGGL((k_sweep<NC, false>), dim3(1), dim3(Shape<NC>::LANES), 0, st, a, pb);
   return hipGetLastError();
 }
 
 hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
   const int Mc = 2 * ((Nc - 1) / 3) + 1;
-  if (Mc > CONV_MMAX) return hipErrorInvalidValue;
+  if (Mc > CONV_MMAX || pb.scheme != 0) return hipErrorInvalidValue;  // SBDF2 only
   hipLaunchKernelGGL(k_sweep_conv, dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc);
   return hipGetLastError();
 }
@@ -1198,6 +1311,7 @@ hipError_t sweep_conv_jobs(const SweepJob* d_jobs, int njobs, bool lds_resident,
 }
 
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
+  if (pb.scheme == 1 && a.Rc == nullptr) return hipErrorInvalidValue;  // stage sums needed
   switch (Nc) {
     case 16: return launch_sweep<16>(a, pb, st);
     case 32: return launch_sweep<32>(a, pb, st);

@@ -9,6 +9,9 @@
 namespace pd {
 
 enum { PATH_MULTI = 0, PATH_SINGLE_WG = 1 };
+// row-phase modes: 0 start of a slice, 1 SBDF1, 2 SBDF2, ROW_RK + j end of
+// ARS(4,4,3) stage j = 1..4
+enum { ROW_RK = 10 };
 
 // Per-launch physical and step parameters.
 struct Problem {
@@ -17,6 +20,7 @@ struct Problem {
   double dt;   // step size
   double amp;  // flow amplitude: 0 (none), 1 (Roberts), sqrt(3/2) (GP)
   int tdep;    // 1: Galloway-Proctor phases (cos t, sin t); 0: steady
+  int scheme = 0;  // 0: SBDF1-started SBDF2; 1: ARS(4,4,3) IMEX Runge-Kutta
 };
 
 // A batch of fields stepped together (all of grid size N).
@@ -27,6 +31,7 @@ struct FieldBatch {
   cplx* T2 = nullptr;          // [f][3][M][N] row workspace
   const double* t0 = nullptr;  // [f] start time of each field's slice
   const cplx* tw = nullptr;    // [N] twiddles e^{-2 pi i m/N}
+  cplx* R = nullptr;           // [f][4][3][M][M] Runge-Kutta stage sums (scheme 1 only)
   // optional (null: use the Problem's scalars / the identity map)
   const double* fRm = nullptr;  // [f] per-field Rm
   const double* fkz = nullptr;  // [f] per-field kz
@@ -44,6 +49,7 @@ struct SweepArgs {
   cplx* Gold = nullptr;         // [P][3][M][M] previous coarse results
   const cplx* Uprev = nullptr;  // [3][M][M] U^{k-1}_P (defect; the batched sweep fills it)
   cplx *Bc = nullptr, *Hc = nullptr, *T1c = nullptr, *T2c = nullptr;  // coarse workspaces
+  cplx* Rc = nullptr;           // [4][3][Mc][Mc] coarse Runge-Kutta stage sums (scheme 1)
   const cplx* twc = nullptr;    // coarse twiddles
   double* red = nullptr;        // [2] defect sums (may be null)
   const double* ftab = nullptr; // [P][nsteps][4] cos(py), sin(py), cos(px), sin(px) of the

@@ -108,6 +108,7 @@ hipError_t coarse_one(pd_ctx* c, const cplx* D, cplx* g, int n, hipStream_t st) 
   sa.T1c = c->T1c.as<cplx>();
   sa.T2c = c->T2c.as<cplx>();
   sa.twc = c->twc.as<cplx>();
+  sa.Rc = c->Rc.as<cplx>();
   sa.red = nullptr;
   sa.ftab = c->ftab.as<double>();
   sa.dT = c->dT;
@@ -117,7 +118,7 @@ hipError_t coarse_one(pd_ctx* c, const cplx* D, cplx* g, int n, hipStream_t st) 
   sa.nbase = n;
   sa.nsteps = c->nc;
   sa.mode = 0;
-  const pd::Problem pc = make_problem(c, c->dtc);
+  const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c);
   return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
 }
 
@@ -261,13 +262,19 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
   sa.T1c = c->T1c.as<cplx>();
   sa.T2c = c->T2c.as<cplx>();
   sa.twc = c->twc.as<cplx>();
+  sa.Rc = c->Rc.as<cplx>();
   sa.red = c->red.as<double>();
   sa.ftab = c->ftab.as<double>();
   sa.dT = c->dT;
   sa.M = c->M;
   sa.P = P;
   sa.nsteps = c->nc;
-  const pd::Problem pc = make_problem(c, c->dtc), pf = make_problem(c, c->dtf);
+  const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
+                    pf = make_problem(c, c->dtf, c->scheme_f);
+  {
+    pd_status rs = ensure_rk_buffers(c);
+    if (rs != PD_OK) return rs;
+  }
   auto sweep = [&]() {
     return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
   };
@@ -294,6 +301,7 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
       fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
       fb.t0 = c->t0s.as<double>() + n0;
       fb.tw = c->tw.as<cplx>();
+      if (c->scheme_f == PD_SCHEME_RK443) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
       PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
       sa.n0 = n0;
       sa.mode = 1;
@@ -337,9 +345,9 @@ pd_status pd_lg_add_samples(pd_ctx* c, int n, const double* t0, const void* d_D,
   DevBuf fF, fG;
   PD_HIP(c, fF.ensure(sizeof(cplx) * full * n), "alloc");
   PD_HIP(c, fG.ensure(sizeof(cplx) * full * n), "alloc");
-  pd_status s = run_propagator(c, t0, n, c->dtf, c->nf, c->N, d_D, fF.p, st);
+  pd_status s = run_propagator(c, t0, n, c->dtf, c->nf, c->N, d_D, fF.p, st, c->scheme_f);
   if (s != PD_OK) return s;
-  s = run_propagator(c, t0, n, c->dtc, c->nc, c->Nc, d_D, fG.p, st);
+  s = run_propagator(c, t0, n, c->dtc, c->nc, c->Nc, d_D, fG.p, st, c->scheme_c);
   if (s != PD_OK) return s;
   PD_HIP(c, g.Dn.ensure(sizeof(cplx) * box * (n > 2 ? n : 2)), "alloc");
   PD_HIP(c, g.fn.ensure(sizeof(cplx) * box * n), "alloc");

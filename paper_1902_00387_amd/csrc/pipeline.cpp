@@ -88,11 +88,13 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   sa.T1c = c->T1c.as<cplx>();
   sa.T2c = c->T2c.as<cplx>();
   sa.twc = c->twc.as<cplx>();
+  sa.Rc = c->Rc.as<cplx>();
   sa.ftab = c->ftab.as<double>();
   sa.dT = c->dT;
   sa.M = c->M;
   sa.nsteps = c->nc;
-  const pd::Problem pc = make_problem(c, c->dtc), pf = make_problem(c, c->dtf);
+  const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
+                    pf = make_problem(c, c->dtf, c->scheme_f);
   auto sweep = [&]() -> hipError_t {
     return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, cs) : pd::sweep(c->Nc, sa, pc, cs);
   };
@@ -141,6 +143,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
         fb.T2 = c->T2f.as<cplx>() + (size_t)a * rows;
         fb.t0 = c->t0s.as<double>() + a;
         fb.tw = c->tw.as<cplx>();
+        if (c->scheme_f == PD_SCHEME_RK443) fb.R = c->Rf.as<cplx>() + (size_t)4 * a * box;
         int path = choose_path(c, b - a);
         if (path == PD_PATH_MULTI2) path = PD_PATH_MULTI;  // the chunks already use two streams
         PD_HIP(c, pd::propagate(c->N, fb, pf, b - a, c->nf, path, st), "fine sweep");

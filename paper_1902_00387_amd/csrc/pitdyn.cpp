@@ -42,19 +42,32 @@ pd_status hipfail(pd_ctx* c, hipError_t e, const char* what) {
   return fail(c, PD_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-pd::Problem make_problem(const pd_ctx* c, double dt) {
+pd::Problem make_problem(const pd_ctx* c, double dt, int scheme) {
   pd::Problem pb;
   pb.Rm = c->Rm;
   pb.kz = c->kz;
   pb.dt = dt;
   pb.amp = c->flow == PD_FLOW_NONE ? 0.0 : (c->flow == PD_FLOW_ROBERTS ? 1.0 : std::sqrt(1.5));
   pb.tdep = c->flow == PD_FLOW_GP ? 1 : 0;
+  pb.scheme = scheme == PD_SCHEME_RK443 ? 1 : 0;
   return pb;
 }
 
+// the convolution form of the coarse sweep steps SBDF2 only
 bool use_conv_sweep(const pd_ctx* c) {
-  if (c->coarse_form == PD_COARSE_FFT) return false;
+  if (c->coarse_form == PD_COARSE_FFT || c->scheme_c == PD_SCHEME_RK443) return false;
   return c->Nc <= 64;
+}
+
+// stage-sum buffers of the Runge-Kutta steppers for the slice arrays and the
+// coarse sweep (none for SBDF2)
+pd_status ensure_rk_buffers(pd_ctx* c) {
+  if (!c->have_time) return PD_OK;
+  if (c->scheme_f == PD_SCHEME_RK443)
+    PD_HIP(c, c->Rf.ensure((size_t)4 * c->box_elems() * c->P * sizeof(cplx)), "alloc");
+  if (c->scheme_c == PD_SCHEME_RK443)
+    PD_HIP(c, c->Rc.ensure((size_t)4 * 3 * c->Mc * c->Mc * sizeof(cplx)), "alloc");
+  return PD_OK;
 }
 
 int choose_path(const pd_ctx* c, int nfields) {
@@ -88,7 +101,7 @@ pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStre
 // Propagate `batch` full-layout fields by nsteps steps of dt on grid N (with
 // restriction to Ngrid <= N and zero-padding back when Ngrid < N).
 pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
-                         int Ngrid, const void* d_in, void* d_out, hipStream_t st) {
+                         int Ngrid, const void* d_in, void* d_out, hipStream_t st, int scheme) {
   if (!c->have_problem) return fail(c, PD_ESTATE, "pd_set_problem not called");
   if (batch < 0 || batch > 65535) return fail(c, PD_EINVAL, "batch must be in [0, 65535]");
   if (batch == 0) return PD_OK;
@@ -129,7 +142,11 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
   fb.T2 = c->wT2.as<cplx>();
   fb.t0 = c->wt0.as<double>();
   fb.tw = twb->as<cplx>();
-  const pd::Problem pb = make_problem(c, dt);
+  if (scheme == PD_SCHEME_RK443) {
+    PD_HIP(c, c->wR.ensure(4 * box * batch * sizeof(cplx)), "alloc");
+    fb.R = c->wR.as<cplx>();
+  }
+  const pd::Problem pb = make_problem(c, dt, scheme);
   if (Ngrid == c->N) {
     PD_HIP(c, fine_batch(c, fb, pb, batch, nsteps, st), "propagate");
   } else {
@@ -196,7 +213,7 @@ void pd_destroy(pd_ctx* c) {
     c->tw.release(); c->twc.release(); c->U.release(); c->Fo.release(); c->Gold.release();
     c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
     c->Bc.release(); c->Hc.release(); c->T1c.release(); c->T2c.release(); c->red.release();
-    c->ftab.release();
+    c->ftab.release(); c->Rf.release(); c->Rc.release(); c->wR.release();
     c->flag.release(); c->wB.release(); c->wH.release(); c->wT1.release(); c->wT2.release();
     c->wt0.release();
   }
@@ -227,10 +244,25 @@ pd_status pd_set_path(pd_ctx* c, pd_path p) {
   return PD_OK;
 }
 
+pd_status pd_set_scheme(pd_ctx* c, pd_scheme fine, pd_scheme coarse) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  for (int v : {(int)fine, (int)coarse})
+    if (v != PD_SCHEME_SBDF2 && v != PD_SCHEME_RK443) return fail(c, PD_EINVAL, "unknown scheme %d", v);
+  if (coarse == PD_SCHEME_RK443 && c->coarse_form == PD_COARSE_CONV)
+    return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
+  c->scheme_f = fine;
+  c->scheme_c = coarse;
+  DeviceGuard dg(c->device);
+  return ensure_rk_buffers(c);
+}
+
 pd_status pd_set_coarse_form(pd_ctx* c, pd_coarse_form f) {
   if (!c) return PD_EINVAL;
   if (f != PD_COARSE_AUTO && f != PD_COARSE_FFT && f != PD_COARSE_CONV)
     return fail(c, PD_EINVAL, "unknown coarse form %d", (int)f);
+  if (f == PD_COARSE_CONV && c->scheme_c == PD_SCHEME_RK443)
+    return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
   if (f == PD_COARSE_CONV && c->have_time && c->Nc > 64)
     return fail(c, PD_EINVAL, "the convolution coarse sweep needs N_coarse <= 64");
   c->coarse_form = f;
@@ -323,7 +355,7 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
     PD_HIP(c, hipMemcpy(c->ftab.p, ft.data(), ft.size() * sizeof(double), hipMemcpyHostToDevice), "copy");
   }
   c->have_time = true;
-  return PD_OK;
+  return ensure_rk_buffers(c);
 }
 
 pd_status pd_set_initial_dev(pd_ctx* c, const void* d_b0, void* s) {
@@ -372,7 +404,8 @@ pd_status pd_steps_dev(pd_ctx* c, const double* t0, int batch, double dt, int n_
                        const void* d_in, void* d_out, void* s) {
   if (!c) return PD_EINVAL;
   c->err.clear();
-  return run_propagator(c, t0, batch, dt, n_steps, c->N, d_in, d_out, static_cast<hipStream_t>(s));
+  return run_propagator(c, t0, batch, dt, n_steps, c->N, d_in, d_out, static_cast<hipStream_t>(s),
+                        c->scheme_f);
 }
 
 pd_status pd_fine_dev(pd_ctx* c, const double* t0, int batch, const void* d_in, void* d_out,
@@ -380,7 +413,8 @@ pd_status pd_fine_dev(pd_ctx* c, const double* t0, int batch, const void* d_in, 
   if (!c) return PD_EINVAL;
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
-  return run_propagator(c, t0, batch, c->dtf, c->nf, c->N, d_in, d_out, static_cast<hipStream_t>(s));
+  return run_propagator(c, t0, batch, c->dtf, c->nf, c->N, d_in, d_out, static_cast<hipStream_t>(s),
+                        c->scheme_f);
 }
 
 pd_status pd_coarse_dev(pd_ctx* c, const double* t0, int batch, const void* d_in, void* d_out,
@@ -388,7 +422,8 @@ pd_status pd_coarse_dev(pd_ctx* c, const double* t0, int batch, const void* d_in
   if (!c) return PD_EINVAL;
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
-  return run_propagator(c, t0, batch, c->dtc, c->nc, c->Nc, d_in, d_out, static_cast<hipStream_t>(s));
+  return run_propagator(c, t0, batch, c->dtc, c->nc, c->Nc, d_in, d_out, static_cast<hipStream_t>(s),
+                        c->scheme_c);
 }
 
 pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
@@ -412,6 +447,10 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   if (kres >= 0 && max_iter <= kres)
     return fail(c, PD_EINVAL, "max_iter must exceed the resumed iteration %d", kres);
   c->resume_k = -1;
+  {
+    pd_status rs = ensure_rk_buffers(c);
+    if (rs != PD_OK) return rs;
+  }
   if (!learned && c->pipe_chunks > 1) return parareal_pipelined(c, tol, max_iter, kres, rep);
   pd_report r;
   std::memset(&r, 0, sizeof r);
@@ -433,13 +472,15 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   sa.T1c = c->T1c.as<cplx>();
   sa.T2c = c->T2c.as<cplx>();
   sa.twc = c->twc.as<cplx>();
+  sa.Rc = c->Rc.as<cplx>();
   sa.red = c->red.as<double>();
   sa.ftab = c->ftab.as<double>();
   sa.dT = c->dT;
   sa.M = c->M;
   sa.P = P;
   sa.nsteps = c->nc;
-  const pd::Problem pc = make_problem(c, c->dtc), pf = make_problem(c, c->dtf);
+  const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
+                    pf = make_problem(c, c->dtf, c->scheme_f);
 
   // initial coarse run (Section 3: U^0_n from G over [0, T])
   sa.n0 = 0;
@@ -479,6 +520,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
     fb.t0 = c->t0s.as<double>() + n0;
     fb.tw = c->tw.as<cplx>();
+    if (c->scheme_f == PD_SCHEME_RK443) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
     PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
     PD_HIP(c, hipEventRecord(ev[1], st), "event");
     // serial coarse sweep with the correction, then the defect sums
