@@ -166,12 +166,12 @@ def run_batch(args):
         b.add("gp", it["Rm"], it["kz"], it["N"], it["T"], it["P"], it["dtf"], it["dtc"], it["Nc"],
               initial_field(it["N"], it["kz"], it["seed"]))
     print(f"# batch: {len(inst)} instances", file=sys.stderr, flush=True)
-    st = b.run(TOL, 32, use_graph=True)   # first run builds buffers and captures the graph
+    st = b.run(TOL, 33, use_graph=True)   # first run builds buffers and captures the graph
     torch.cuda.synchronize()
     times = []
     for _ in range(max(1, args.steps)):
         t0 = time.perf_counter()
-        st = b.run(TOL, 32, use_graph=True)
+        st = b.run(TOL, 33, use_graph=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     secs = min(times)
@@ -324,6 +324,201 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _serial_fine(ctx, b0, P, dT):
+    """Serial fine solve on the GPU: slice after slice, batch 1; returns the
+    slice-boundary norms and the seconds taken."""
+    import torch
+    u = b0[None].clone()
+    norms = [float(torch.linalg.vector_norm(u).item())]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(P):
+        u = ctx.fine([n * dT], u)
+        norms.append(float(torch.linalg.vector_norm(u).item()))
+    torch.cuda.synchronize()
+    return norms, time.perf_counter() - t0
+
+
+def _growth(norms, dT):
+    """Least-squares slope of ln|U_n| over n = ceil(P/2)..P (the estimator
+    pd_growth_rate uses)."""
+    import numpy as np
+    P = len(norms) - 1
+    n = np.arange((P + 1) // 2, P + 1)
+    return float(np.polyfit(n * dT, np.log(np.asarray(norms)[n]), 1)[0])
+
+
+def run_nc_sweep(args):
+    """Coarse-grid sweep (the paper's Section 5.2 study, its speed-up-vs-N_C
+    figure): Roberts flow, Rm = 512, kz = 2.87, N_F = 128 or 256 (powers of two
+    around the paper's 160), fine ARS(4,4,3) with dt = 1e-2 (5e-3 on 256^2),
+    10 slices of length 1,
+    tolerance 1e-5 (the paper's accuracy target).  For every N_C the coarse
+    step is the largest of {0.1, 0.05, ..., 0.003125} whose coarse-only run
+    is still as accurate at T as the smallest step allows (error against the
+    serial fine solution within twice the smallest-step error: accuracy
+    limited by the grid, not by the step).  Reported: k_con, R_f/R_c, time
+    to solution, speed-up over the serial fine solve on the same GPU, and the
+    paper's speed-up model (eq. speed_up) for 10 processors."""
+    import numpy as np
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+    N, Rm, kz, P, T, tol = args.nc_nf, 512.0, 2.87, 10, 10.0, args.nc_tol
+    dtf = 1e-2 if N <= 128 else 5e-3  # largest stable fine step (ARS(4,4,3)) of the grid
+    b0 = torch.from_numpy(initial_field(N, kz, 500000)).cuda()
+    ctx = pd.Context(0)
+    ctx.set_problem("roberts", Rm, kz, N)
+    ctx.set_time(T, P, dtf, dtf, N)
+    ctx.set_scheme("rk443", "rk443")
+    u = b0[None].clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for n in range(P):
+        u = ctx.fine([n * T / P], u)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - ts
+    uT = u[0].cpu().numpy()
+    _log(f"# serial fine {serial_s:.3f} s, |b(T)| {np.linalg.norm(uT):.3e}")
+    rows = []
+    for nc in (N // 8, N // 4, N // 2, N):
+        if nc > 128:
+            continue  # one-workgroup coarse sweeps above 128^2 take minutes
+        errs = {}
+        for cand in (0.1, 0.05, 0.025, 0.0125, 0.00625, 0.003125):
+            ctx.set_time(T, P, dtf, cand, nc)
+            ctx.set_initial(b0)
+            ctx.parareal(0.0, 0)
+            g = ctx.get_slices()[P]
+            e = float(np.linalg.norm(g - uT) / np.linalg.norm(uT))
+            errs[cand] = e if np.isfinite(e) else float("inf")
+        emin = min(errs.values())
+        dtc = max(c for c, e in errs.items() if e <= 2.0 * emin)
+        _log(f"# N_C={nc}: coarse-run errors " + ", ".join(f"{c:g}: {e:.2e}" for c, e in errs.items())
+             + f" -> dt_c {dtc:g}")
+        ctx.set_time(T, P, dtf, dtc, nc)
+        ctx.set_initial(b0)
+        ctx.parareal(tol, P + 1)  # warm-up
+        ctx.set_initial(b0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.parareal(tol, P + 1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        # R_f / R_c: one slice of F against one slice of G (batch 1)
+        x = b0[None].clone()
+        for fn in (ctx.fine, ctx.coarse):
+            fn([0.0], x)
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        for _ in range(3):
+            ctx.fine([0.0], x)
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - tf) / 3
+        tc = time.perf_counter()
+        for _ in range(3):
+            ctx.coarse([0.0], x)
+        torch.cuda.synchronize()
+        tc = (time.perf_counter() - tc) / 3
+        k = rep["k_con"]
+        model = 1.0 / ((1.0 + k / P) * (tc / tf) + k / P) if k > 0 else None
+        rows.append({"N_coarse": nc, "dt_coarse": dtc, "coarse_run_error": errs[dtc], "k_con": k,
+                     "sigma": rep["sigma"][:rep["iters"]], "time_s": tp, "Rf_over_Rc": tf / tc,
+                     "speedup_vs_serial_gpu": serial_s / tp, "model_speedup_P10": model})
+        _log(f"# N_C={nc} dt_c={dtc}: k_con {k}, {tp:.3f} s, Rf/Rc {tf / tc:.1f}, "
+             f"speed-up {serial_s / tp:.2f} (model {model})")
+    ctx.close()
+    print(json.dumps({"experiment": "coarse grid sweep", "flow": "roberts", "Rm": Rm, "kz": kz,
+                      "N_coarse_list": [r["N_coarse"] for r in rows],
+                      "N_fine": N, "dt_fine": dtf, "slices": P, "T": T, "scheme": "rk443",
+                      "tol": tol, "serial_fine_gpu_s": serial_s, "rows": rows}), flush=True)
+
+
+def run_work_precision(args):
+    """Work against accuracy of the fine steppers (the paper's Section 5.1
+    comparison): Galloway-Proctor, Rm = 300, N = 256, from t = 0 to 1; error
+    = relative two-norm against ARS(4,4,3) at dt = 1.25e-4; work = explicit
+    evaluations (steps x stages) and GPU time (batch 1)."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+    N, Rm, kz = 256, 300.0, 0.57
+    b0 = torch.from_numpy(initial_field(N, kz, 600000, amp=1.0)).cuda()[None]
+    ctx = pd.Context(0)
+    ctx.set_problem("gp", Rm, kz, N)
+
+    def solve(scheme, dt):
+        ctx.set_scheme(scheme, scheme)
+        n = int(round(1.0 / dt))
+        ctx.steps([0.0], dt, n, b0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = ctx.steps([0.0], dt, n, b0)
+        torch.cuda.synchronize()
+        return y, time.perf_counter() - t0, n
+    ref, _, _ = solve("rk443", 1.25e-4)
+    rn = float(torch.linalg.vector_norm(ref).item())
+    rows = []
+    for scheme, stages in (("sbdf2", 1), ("rk443", 4)):
+        for dt in (1e-2, 5e-3, 2.5e-3, 1.25e-3, 6.25e-4, 2.5e-4):
+            y, secs, n = solve(scheme, dt)
+            err = float(torch.linalg.vector_norm(y - ref).item()) / rn
+            rows.append({"scheme": scheme, "dt": dt, "evaluations": n * stages, "gpu_s": secs,
+                         "rel_error": err})
+            _log(f"# {scheme} dt={dt}: {n * stages} evaluations, {secs * 1e3:.1f} ms, error {err:.3e}")
+    ctx.close()
+    print(json.dumps({"experiment": "work-precision", "flow": "gp", "Rm": Rm, "N": N, "T": 1.0,
+                      "reference": "rk443 dt=1.25e-4", "rows": rows}), flush=True)
+
+
+def run_table1(args):
+    """Growth rates of the paper's Table 1 parameter sets from serial fine
+    solves on the GPU over t in [0, 50] (50 slices of length 1; growth =
+    least-squares slope of ln|b| over the second half).  N_F = 160 of the
+    first row becomes 256 (powers of two only); steppers ARS(4,4,3) except
+    SBDF2 for the dt = 1e-4 row."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+    rows = [("roberts", 512.0, 2.87, 256, 5e-3, "rk443", 0.11),
+            ("roberts", 4096.0, 7.5, 512, 2.5e-3, "rk443", 0.097),
+            ("gp", 3.0, 0.57, 16, 5e-3, "rk443", 0.15),
+            ("gp", 300.0, 0.57, 128, 1e-3, "rk443", 0.3),
+            ("gp", 3000.0, 0.57, 512, 1e-4, "sbdf2", 0.3)]
+    only = set(int(v) for v in args.table1_rows.split(",")) if args.table1_rows else None
+    out = []
+    for i, (flow, Rm, kz, N, dt, scheme, paper) in enumerate(rows):
+        if only is not None and i not in only:
+            continue
+        T, P = 50.0, 50
+        ctx = pd.Context(0)
+        ctx.set_problem(flow, Rm, kz, N)
+        ctx.set_time(T, P, dt, dt, N)
+        ctx.set_scheme(scheme, scheme)
+        b0 = torch.from_numpy(initial_field(N, kz, 700000 + i)).cuda()
+        u = b0[None].clone()
+        norms = [float(torch.linalg.vector_norm(u).item())]
+        t0 = time.perf_counter()
+        for n in range(P):
+            u = ctx.fine([n * 1.0], u)
+            norms.append(float(torch.linalg.vector_norm(u).item()))
+            if n % 10 == 9:
+                _log(f"# table1 row {i} ({flow} Rm={Rm}): slice {n + 1}/{P}, {time.perf_counter() - t0:.1f} s")
+        g = _growth(norms, 1.0)
+        ctx.close()
+        out.append({"flow": flow, "Rm": Rm, "kz": kz, "N": N, "dt": dt, "scheme": scheme,
+                    "growth_rate": g, "paper": paper, "seconds": time.perf_counter() - t0})
+        _log(f"# table1 row {i}: growth {g:.4f} (paper {paper})")
+    print(json.dumps({"experiment": "Table 1 growth rates", "T": 50.0, "rows": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +532,12 @@ def main():
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--learned", action="store_true",
                     help="learned versus plain coarse propagator (256^2, 128 slices)")
+    ap.add_argument("--nc-sweep", action="store_true", help="coarse-grid sweep (Roberts Rm=512)")
+    ap.add_argument("--nc-tol", type=float, default=1e-5, help="defect tolerance of the sweep")
+    ap.add_argument("--nc-nf", type=int, default=128, help="fine grid of the sweep (128 or 256)")
+    ap.add_argument("--work-precision", action="store_true", help="SBDF2 vs ARS(4,4,3) work-precision")
+    ap.add_argument("--table1", action="store_true", help="growth rates of the paper's Table 1 sets")
+    ap.add_argument("--table1-rows", default="", help="comma-separated row indices (default all)")
     ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
     ap.add_argument("--pipeline", type=int, default=-1,
                     help="slice chunks of pipelined Parareal (0/1 off, -1 library default)")
@@ -350,7 +551,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
-              "path here is single-GPU; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "path here is single-GPU (slices would shard across GPUs in contiguous blocks).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -365,6 +566,15 @@ def main():
         return
     if args.learned:
         run_learned(args)
+        return
+    if args.nc_sweep:
+        run_nc_sweep(args)
+        return
+    if args.work_precision:
+        run_work_precision(args)
+        return
+    if args.table1:
+        run_table1(args)
         return
     dev = torch.device("cuda:0")
     b0 = torch.from_numpy(initial_field(N, KZ, SEED)).to(dev)

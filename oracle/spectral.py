@@ -7,7 +7,7 @@ curl(u x B) + Rm^-1 lap B with B = b(x, y, t) exp(i kz z) (2.5D monochromatic
 ansatz, Section 1), so d/dz -> i kz and the problem is 2D and complex on the
 2pi-periodic square (Section 4: Fourier bases, N x N modes).
 
-Conventions (readings of the paper, all listed in the design doc):
+Conventions (readings of the paper where it is silent or ambiguous):
   * coefficients: b(x, y) = sum_k bh[k] exp(i (kx x + ky y)); arrays are
     complex128 ``[3][N][N]`` = [component][ky index][kx index];
   * dealiasing: the explicit term is truncated to the square box
