@@ -541,8 +541,8 @@ def main():
     ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
     ap.add_argument("--pipeline", type=int, default=-1,
                     help="slice chunks of pipelined Parareal (0/1 off, -1 library default)")
-    ap.add_argument("--pipeline-hold-last", action="store_true",
-                    help="pipelined: start the next fine sweep's last chunk only after the defect")
+    ap.add_argument("--pipeline-spec", type=int, default=2,
+                    help="pipelined: 0 hold the last chunk, 1 start all early, 2 predict")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs")
     args = ap.parse_args()
@@ -583,7 +583,7 @@ def main():
     ctx.set_time(T, P, DT_FINE, DT_COARSE, N_COARSE)
     ctx.set_path(args.path)
     if args.pipeline >= 0:
-        ctx.set_pipeline(args.pipeline, not args.pipeline_hold_last)
+        ctx.set_pipeline(args.pipeline, args.pipeline_spec)
     nf = int(round(T / P / DT_FINE))
     # launch shapes of the fine step's kernels, picked by timing on this device
     ctx.set_initial(b0)

@@ -173,19 +173,21 @@ pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int 
 pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
 
 /* Order of the work inside pd_parareal with the plain coarse propagator.
-   chunks >= 2: pipelined -- the serial coarse sweep runs on a stream of its
+   chunks >= 2 (default 3, speculate 2): pipelined -- the serial coarse sweep runs on a stream of its
    own in `chunks` runs of consecutive slices, and the fine sweep of a run of
-   slices (on one of two fine streams) starts as soon as the coarse sweep has
+   slices (on up to three fine streams) starts as soon as the coarse sweep has
    produced its start values, so the fine sweeps of iteration k + 1 overlap
    the coarse sweep of iteration k.  They start before the defect of
-   iteration k is known: every run with speculate_all != 0, all but the last
-   run otherwise; when the iteration stops at k, the call still waits for
-   them and discards their results.  chunks 0 or 1 (the default): every fine
-   sweep, then the coarse sweep, on the context's stream.  Both orders give
-   bitwise the same iterates, defects and k_con; the timings in pd_report add
-   kernel times per stream (they overlap when pipelined).  The learned coarse
-   propagator always runs unpipelined. */
-pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate_all);
+   iteration k is known: speculate = 1 every run, 0 all but the last run,
+   2 every run unless sigma_{k-1}^2 / sigma_{k-2} <= tol predicts that
+   iteration k converges (then none).  When the iteration stops at k, the
+   call still waits for fine sweeps already started and discards them.
+   chunks 0 or 1: every fine sweep, then the coarse sweep, on the context's
+   stream.  Both orders give bitwise the same iterates,
+   defects and k_con; the timings in pd_report add kernel times per stream
+   (they overlap when pipelined).  The learned coarse propagator always runs
+   unpipelined. */
+pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate);
 
 /* Checkpoint and resume.  After k iterations of pd_parareal the whole state
    of the iteration is the slice states U^k_n (pd_get_slices) and, for the

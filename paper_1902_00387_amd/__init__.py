@@ -275,9 +275,10 @@ class Context:
         code = {"sbdf2": 0, "rk443": 1}
         self._ok(lib.pd_set_scheme(self._h, code[fine], code[coarse]))
 
-    def set_pipeline(self, chunks: int, speculate_all: bool = True):
-        """Pipelined Parareal over `chunks` runs of slices (0 or 1: off)."""
-        self._ok(lib.pd_set_pipeline(self._h, int(chunks), int(bool(speculate_all))))
+    def set_pipeline(self, chunks: int, speculate: int = 2):
+        """Pipelined Parareal over `chunks` runs of slices (0 or 1: off);
+        speculate: 0 hold the last run, 1 start every run early, 2 predict."""
+        self._ok(lib.pd_set_pipeline(self._h, int(chunks), int(speculate)))
 
     def get_coarse_values(self) -> np.ndarray:
         out = np.empty((self.P, 3, self.N, self.N), np.complex128)

@@ -21,8 +21,9 @@ struct pd_ctx {
   hipStream_t cst = nullptr;       // pipelined Parareal: coarse sweep stream
   hipStream_t fst = nullptr;       // pipelined Parareal: fine streams
   hipStream_t fst2 = nullptr;
-  int pipe_spec = 1;               // pipelined: start every chunk of the next fine sweep early
-  int pipe_chunks = 0;             // slice chunks of the pipelined Parareal (< 2: off)
+  hipStream_t fst3 = nullptr;
+  int pipe_spec = 2;               // pipelined: which chunks of the next fine sweep start early
+  int pipe_chunks = 3;             // slice chunks of the pipelined Parareal (< 2: off)
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;

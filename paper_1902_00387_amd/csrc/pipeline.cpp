@@ -43,7 +43,7 @@ namespace pd {
 namespace ctxh {
 
 pd_status ensure_pipeline_streams(pd_ctx* c) {
-  for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2})
+  for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2, &c->fst3})
     if (!*p) PD_HIP(c, hipStreamCreateWithFlags(p, hipStreamNonBlocking), "stream");
   return PD_OK;
 }
@@ -62,21 +62,24 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   auto hi = [&](int ch) { return std::min(P, (ch + 1) * Sc); };
   cplx* U = c->U.as<cplx>();
   cplx* Fo = c->Fo.as<cplx>();
-  hipStream_t fs[2] = {c->fst, c->fst2};
+  // up to three fine streams: a chunk's fine launches are latency-bound, so
+  // chunks must run side by side to keep the chip as busy as one full sweep
+  hipStream_t fs[3] = {c->fst, c->fst2, c->fst3};
+  const int NFS = std::min(C, 3);
   hipStream_t cs = c->cst;
 
   // per parity of the iteration and chunk: fine start, start values copied,
   // fine end, coarse start, coarse end; then the join events
   Events E;
-  PD_HIP(c, E.make((size_t)10 * C + 4), "event");
+  PD_HIP(c, E.make((size_t)10 * C + 5), "event");
   auto ev = [&](int kind, int k, int ch) { return E.ev[((size_t)kind * 2 + (k & 1)) * C + ch]; };
   auto Fs = [&](int k, int ch) { return ev(0, k, ch); };
   auto Fc = [&](int k, int ch) { return ev(1, k, ch); };
   auto Fe = [&](int k, int ch) { return ev(2, k, ch); };
   auto Gs = [&](int k, int ch) { return ev(3, k, ch); };
   auto Ge = [&](int k, int ch) { return ev(4, k, ch); };
-  hipEvent_t evIn = E.ev[10 * C], evRed = E.ev[10 * C + 1], evF0 = E.ev[10 * C + 2],
-             evF1 = E.ev[10 * C + 3];
+  hipEvent_t evIn = E.ev[10 * C], evRed = E.ev[10 * C + 1];
+  hipEvent_t evJoin[3] = {E.ev[10 * C + 2], E.ev[10 * C + 3], E.ev[10 * C + 4]};
 
   pd::SweepArgs sa;
   sa.U = U;
@@ -102,8 +105,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   // everything earlier on the caller's stream comes first
   PD_HIP(c, hipEventRecord(evIn, c->stream), "event");
   PD_HIP(c, hipStreamWaitEvent(cs, evIn, 0), "wait");
-  PD_HIP(c, hipStreamWaitEvent(fs[0], evIn, 0), "wait");
-  PD_HIP(c, hipStreamWaitEvent(fs[1], evIn, 0), "wait");
+  for (int i = 0; i < NFS; ++i) PD_HIP(c, hipStreamWaitEvent(fs[i], evIn, 0), "wait");
 
   pd_report r;
   std::memset(&r, 0, sizeof r);
@@ -126,7 +128,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   auto enqueue_fine = [&](int k, int c0, int c1) -> pd_status {
     const int n0 = std::min(k - 1, P - 1);
     for (int ch = c0; ch < c1; ++ch) {
-      hipStream_t st = fs[ch & 1];
+      hipStream_t st = fs[ch % NFS];
       PD_HIP(c, hipStreamWaitEvent(st, Ge(k - 1, ch), 0), "wait");
       PD_HIP(c, hipEventRecord(Fs(k, ch), st), "event");
       const int a = std::max(lo(ch), n0), b = hi(ch);
@@ -188,10 +190,16 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
     PD_HIP(c, hipMemcpyAsync(c->hred, c->red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, cs), "copy");
     PD_HIP(c, hipEventRecord(evRed, cs), "event");
     // the next iteration's fine sweeps go ahead chunk by chunk while this
-    // iteration's coarse sweep runs (all but the last chunk with spec = 1)
+    // iteration's coarse sweep runs: every chunk (speculate 1), all but the
+    // last (0), or every chunk unless the defects so far predict that this
+    // iteration converges, sigma_{k-1}^2 / sigma_{k-2} <= tol (2)
     fine_done = 0;
     if (k < max_iter && C > 1) {
-      const int ahead = c->pipe_spec ? C : C - 1;
+      int ahead = c->pipe_spec == 0 ? C - 1 : C;
+      if (c->pipe_spec == 2 && k >= 3) {
+        const double s1 = r.sigma[k - 2], s2 = r.sigma[k - 3];
+        if (s2 > 0.0 && s1 * s1 / s2 <= tol) ahead = 0;
+      }
       s = enqueue_fine(k + 1, 0, ahead);
       if (s != PD_OK) return s;
       fine_done = ahead;
@@ -220,11 +228,11 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   if (max_iter == 0) status = PD_OK;
   // join: later work on the caller's stream follows everything above
   // (including fine sweeps of an iteration that was not needed)
-  PD_HIP(c, hipEventRecord(evF0, fs[0]), "event");
-  PD_HIP(c, hipEventRecord(evF1, fs[1]), "event");
+  for (int i = 0; i < NFS; ++i) {
+    PD_HIP(c, hipEventRecord(evJoin[i], fs[i]), "event");
+    PD_HIP(c, hipStreamWaitEvent(c->stream, evJoin[i], 0), "wait");
+  }
   PD_HIP(c, hipEventRecord(evRed, cs), "event");
-  PD_HIP(c, hipStreamWaitEvent(c->stream, evF0, 0), "wait");
-  PD_HIP(c, hipStreamWaitEvent(c->stream, evF1, 0), "wait");
   PD_HIP(c, hipStreamWaitEvent(c->stream, evRed, 0), "wait");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
   r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();

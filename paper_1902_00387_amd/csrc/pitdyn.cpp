@@ -201,7 +201,7 @@ void pd_destroy(pd_ctx* c) {
       (void)hipStreamSynchronize(c->side);
       (void)hipStreamDestroy(c->side);
     }
-    for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2})
+    for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2, &c->fst3})
       if (*p) {
         (void)hipStreamSynchronize(*p);
         (void)hipStreamDestroy(*p);
@@ -228,11 +228,12 @@ pd_status pd_set_stream(pd_ctx* c, void* s) {
   return PD_OK;
 }
 
-pd_status pd_set_pipeline(pd_ctx* c, int chunks, int speculate_all) {
+pd_status pd_set_pipeline(pd_ctx* c, int chunks, int speculate) {
   if (!c) return PD_EINVAL;
   if (chunks < 0 || chunks > 64) return fail(c, PD_EINVAL, "chunks must be in [0, 64]");
+  if (speculate < 0 || speculate > 2) return fail(c, PD_EINVAL, "speculate must be 0, 1 or 2");
   c->pipe_chunks = chunks;
-  c->pipe_spec = speculate_all != 0;
+  c->pipe_spec = speculate;
   return PD_OK;
 }
 

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 
 def run(lib, chunks, P=10, N=32, tol=1e-10, max_iter=None, flow="gp", Nc=16, resume=None, form=0,
-        spec=True):
+        spec=2):
     with lib.Context(0) as ctx:
         ctx.set_problem(flow, 60.0, 0.57, N)
         ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, Nc)
@@ -30,8 +30,7 @@ def run(lib, chunks, P=10, N=32, tol=1e-10, max_iter=None, flow="gp", Nc=16, res
         return rep, ctx.get_slices(), ctx.get_coarse_values()
 
 
-@pytest.mark.parametrize("chunks,spec", [(2, True), (3, True), (4, False), (7, True), (10, False),
-                                         (64, True)])
+@pytest.mark.parametrize("chunks,spec", [(2, 1), (3, 2), (4, 0), (7, 1), (10, 2), (64, 1)])
 def test_pipelined_equals_plain_order_bitwise(lib, chunks, spec):
     r0, U0, G0 = run(lib, 0)
     r1, U1, G1 = run(lib, chunks, spec=spec)
