@@ -47,12 +47,13 @@ def propagate(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
     return b
 
 
-# ARS(4,4,3): the four-stage, third-order, L-stable and stiffly accurate IMEX
-# Runge-Kutta pair of Ascher, Ruuth & Spiteri (1997), the "RK443" the paper
-# steps with (Section 4; Section 5.1 compares it with lower-order pairs).
-# Stage i (i = 1..5, stage 1 = the step's start value) solves
+# IMEX Runge-Kutta pairs of Ascher, Ruuth & Spiteri (1997): ARS(4,4,3) is
+# the "RK443" the paper steps with (Section 4; Section 5.1 compares it with
+# the lower-order RK111 = ARS(1,1,1) and RK222 = ARS(2,2,2)).  For a pair
+# with s explicit stages, stage i = 1..s+1 (stage 1 = the step's start value)
+# solves
 #   X_i = b_n + dt sum_{j<i} A_ij N(X_j, t + C_j dt) + dt sum_{j<=i} AT_ij L X_j,
-# L = -|k|^2/Rm diagonal, and both parts are stiffly accurate: b_{n+1} = X_5.
+# L = -|k|^2/Rm diagonal; all three are stiffly accurate: b_{n+1} = X_{s+1}.
 from fractions import Fraction as _Fr
 
 RK443_C = (_Fr(0), _Fr(1, 2), _Fr(2, 3), _Fr(1, 2), _Fr(1))
@@ -71,43 +72,71 @@ RK443_AT = (  # implicit part, lower triangular with diagonal 1/2 (first row and
     (_Fr(0), _Fr(3, 2), _Fr(-3, 2), _Fr(1, 2), _Fr(1, 2)),
 )
 
+# ARS(2,2,2): gamma = 1 - 1/sqrt(2), delta = 1 - 1/(2 gamma) (irrational, so floats)
+_G2 = 1.0 - 1.0 / np.sqrt(2.0)
+_D2 = 1.0 - 1.0 / (2.0 * _G2)
+RK222_C = (0.0, _G2, 1.0)
+RK222_A = ((), (_G2,), (_D2, 1.0 - _D2))
+RK222_AT = ((0.0,), (0.0, _G2), (0.0, 1.0 - _G2, _G2))
 
-def propagate_rk443(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
-                    dt: float, nsteps: int) -> np.ndarray:
-    """Advance one field ``[3][N][N]`` by ``nsteps`` ARS(4,4,3) steps of size
-    ``dt`` from time ``t0`` (step j starts at t0 + j dt, a product; stage i
-    of it evaluates the flow at t0 + j dt + C_i dt).  A one-step method, so
-    nothing restarts at slice boundaries."""
+# ARS(1,1,1): forward-backward Euler
+RK111_C = (_Fr(0), _Fr(1))
+RK111_A = ((), (_Fr(1),))
+RK111_AT = ((_Fr(0),), (_Fr(0), _Fr(1)))
+
+RK_TABLEAUS = {
+    "rk443": (RK443_C, RK443_A, RK443_AT),
+    "rk222": (RK222_C, RK222_A, RK222_AT),
+    "rk111": (RK111_C, RK111_A, RK111_AT),
+}
+
+
+def propagate_imex_rk(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
+                      dt: float, nsteps: int, scheme: str = "rk443") -> np.ndarray:
+    """Advance one field ``[3][N][N]`` by ``nsteps`` steps of the IMEX
+    Runge-Kutta pair ``scheme`` with size ``dt`` from time ``t0`` (step j
+    starts at t0 + j dt, a product; stage i of it evaluates the flow at
+    t0 + j dt + C_i dt).  One-step methods: nothing restarts at slice
+    boundaries."""
     if nsteps < 1:
         raise ValueError("nsteps must be >= 1")
+    Ct, At, ATt = RK_TABLEAUS[scheme]
+    S = len(Ct)  # stages including the start value
     N = bh.shape[-1]
     L = -sp.k_squared(N, kz) / Rm
-    A = [[float(v) for v in row] for row in RK443_A]
-    AT = [[float(v) for v in row] for row in RK443_AT]
-    C = [float(v) for v in RK443_C]
+    A = [[float(v) for v in row] for row in At]
+    AT = [[float(v) for v in row] for row in ATt]
+    C = [float(v) for v in Ct]
     b = np.array(bh, dtype=np.complex128)
     for j in range(nsteps):
         t = t0 + j * dt
         X, NX = [], []
-        for i in range(5):
+        for i in range(S):
             rhs = b.copy()
             for m in range(i):
                 rhs = rhs + dt * (A[i][m] * NX[m] + AT[i][m] * L * X[m])
             Xi = rhs / (1.0 - dt * AT[i][i] * L) if AT[i][i] != 0.0 else rhs
             X.append(Xi)
-            if i < 4:
+            if i < S - 1:
                 NX.append(sp.explicit_term(Xi, flow, kz, t + C[i] * dt))
-        b = X[4]
+        b = X[S - 1]
     return b
+
+
+def propagate_rk443(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
+                    dt: float, nsteps: int) -> np.ndarray:
+    """``propagate_imex_rk`` with ARS(4,4,3)."""
+    return propagate_imex_rk(bh, flow, Rm, kz, t0, dt, nsteps, "rk443")
 
 
 def propagate_scheme(bh: np.ndarray, flow: str, Rm: float, kz: float, t0: float,
                      dt: float, nsteps: int, scheme: str = "sbdf2") -> np.ndarray:
-    """``propagate`` (scheme "sbdf2") or ``propagate_rk443`` ("rk443")."""
+    """``propagate`` (scheme "sbdf2") or ``propagate_imex_rk`` ("rk443",
+    "rk222", "rk111")."""
     if scheme == "sbdf2":
         return propagate(bh, flow, Rm, kz, t0, dt, nsteps)
-    if scheme == "rk443":
-        return propagate_rk443(bh, flow, Rm, kz, t0, dt, nsteps)
+    if scheme in RK_TABLEAUS:
+        return propagate_imex_rk(bh, flow, Rm, kz, t0, dt, nsteps, scheme)
     raise ValueError(f"unknown scheme {scheme!r}")
 
 

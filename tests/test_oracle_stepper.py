@@ -171,3 +171,30 @@ def test_rk443_slice_solver_and_scheme_switch():
     assert np.array_equal(F(b0, 0.0), stepper.propagate_rk443(b0, "roberts", 10.0, kz, 0.0, 0.05, 10))
     with pytest.raises(ValueError):
         stepper.propagate_scheme(b0, "roberts", 10.0, kz, 0.0, 0.05, 1, "rk4")
+
+
+def test_rk222_and_rk111_tableaus_and_orders():
+    """ARS(2,2,2): order-2 conditions of both parts and their coupling (floats,
+    gamma irrational); ARS(1,1,1): a single step is the SBDF1 step exactly in
+    exact arithmetic (forward-backward Euler), and to rounding in floats.
+    Self-convergence orders 2 and 1 with the Galloway-Proctor flow."""
+    C, A, AT = stepper.RK222_C, stepper.RK222_A, stepper.RK222_AT
+    A = [list(r) + [0.0] * (3 - len(r)) for r in A]
+    AT = [list(r) + [0.0] * (3 - len(r)) for r in AT]
+    b, bt = A[2], AT[2]
+    for i in range(3):
+        assert abs(sum(A[i]) - C[i]) < 1e-15 and abs(sum(AT[i]) - C[i]) < 1e-15
+    for w in (b, bt):
+        assert abs(sum(w) - 1.0) < 1e-15
+        assert abs(sum(w[i] * C[i] for i in range(3)) - 0.5) < 1e-15
+    assert abs(AT[1][1] - AT[2][2]) < 1e-15 and abs(AT[1][1] - (1 - 2 ** -0.5)) < 1e-15
+    N, kz = 16, 0.57
+    b0 = initial_field(N, kz, 12, amp=1.0)
+    one = stepper.propagate_imex_rk(b0, "gp", 3.0, kz, 0.3, 0.02, 1, "rk111")
+    sb1 = stepper.propagate(b0, "gp", 3.0, kz, 0.3, 0.02, 1)
+    assert np.linalg.norm(one - sb1) <= 1e-15 * np.linalg.norm(sb1)
+    for scheme, lo, hi in (("rk222", 3.5, 4.5), ("rk111", 1.8, 2.2)):
+        sols = [stepper.propagate_imex_rk(b0, "gp", 3.0, kz, 0.3, 0.5 / n, n, scheme)
+                for n in (40, 80, 160)]
+        d = [np.linalg.norm(sols[i] - sols[i + 1]) for i in range(2)]
+        assert lo < d[0] / d[1] < hi, (scheme, d)
