@@ -441,7 +441,8 @@ def run_nc_sweep(args):
 
 def run_work_precision(args):
     """Work against accuracy of the fine steppers (the paper's Section 5.1
-    comparison): Galloway-Proctor, Rm = 300, N = 256, from t = 0 to 1; error
+    comparison of RK111, RK222 and RK443, plus SBDF2): Galloway-Proctor,
+    Rm = 300, N = 256, from t = 0 to 1; error
     = relative two-norm against ARS(4,4,3) at dt = 1.25e-4; work = explicit
     evaluations (steps x stages) and GPU time (batch 1)."""
     import torch
@@ -465,7 +466,7 @@ def run_work_precision(args):
     ref, _, _ = solve("rk443", 1.25e-4)
     rn = float(torch.linalg.vector_norm(ref).item())
     rows = []
-    for scheme, stages in (("sbdf2", 1), ("rk443", 4)):
+    for scheme, stages in (("sbdf2", 1), ("rk111", 1), ("rk222", 2), ("rk443", 4)):
         for dt in (1e-2, 5e-3, 2.5e-3, 1.25e-3, 6.25e-4, 2.5e-4):
             y, secs, n = solve(scheme, dt)
             err = float(torch.linalg.vector_norm(y - ref).item()) / rn

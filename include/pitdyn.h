@@ -87,8 +87,10 @@ typedef enum {
    diffusion).  Both restart from the slice's start value in every slice. */
 typedef enum {
   PD_SCHEME_SBDF2 = 0,  /* one SBDF1 step, then SBDF2 (multistep, restarted) */
-  PD_SCHEME_RK443 = 1   /* ARS(4,4,3) IMEX Runge-Kutta, the paper's RK443:
-                           four explicit evaluations a step */
+  PD_SCHEME_RK443 = 1,  /* ARS(4,4,3) IMEX Runge-Kutta, the paper's RK443:
+                           four explicit evaluations a step, third order */
+  PD_SCHEME_RK222 = 2,  /* ARS(2,2,2) (RK222): two evaluations, second order */
+  PD_SCHEME_RK111 = 3   /* ARS(1,1,1) (RK111), forward-backward Euler */
 } pd_scheme;
 
 #define PD_MAX_ITER 256

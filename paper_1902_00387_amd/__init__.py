@@ -271,8 +271,9 @@ class Context:
         return out
 
     def set_scheme(self, fine: str = "sbdf2", coarse: str = "sbdf2"):
-        """Time steppers of F and G: "sbdf2" or "rk443" (ARS(4,4,3))."""
-        code = {"sbdf2": 0, "rk443": 1}
+        """Time steppers of F and G: "sbdf2", or the IMEX Runge-Kutta pairs
+        "rk443" (ARS(4,4,3)), "rk222", "rk111"."""
+        code = {"sbdf2": 0, "rk443": 1, "rk222": 2, "rk111": 3}
         self._ok(lib.pd_set_scheme(self._h, code[fine], code[coarse]))
 
     def set_pipeline(self, chunks: int, speculate: int = 2):

@@ -73,47 +73,34 @@ __device__ __forceinline__ FlowPhase flow_phase(const Problem& pb, double t) {
 }
 
 // ---------------------------------------------------------------------------
-// ARS(4,4,3) (Ascher, Ruuth & Spiteri 1997; the paper's RK443, Section 4):
-// stage i = 1..5 has time t + c_i dt and solves
-//   X_i = b_n + dt sum_{j<i} (a_ij N(X_j) + at_ij L X_j) + dt at_ii L X_i,
-// L = -|k|^2/Rm, at_ii = 1/2 for i >= 2; both parts are stiffly accurate,
-// so b_{n+1} = X_5.  The stage sums R_i (i = 2..5) collect the j < i terms
-// as the stages go; X_i = R_i / (1 - dt L / 2).
-__host__ __device__ constexpr double ars_c(int i) {
-  return i == 1 ? 0.0 : i == 2 ? 0.5 : i == 3 ? 2.0 / 3.0 : i == 4 ? 0.5 : 1.0;
-}
-__host__ __device__ constexpr double ars_a(int i, int j) {  // explicit part, j < i
-  return i == 2 ? (j == 1 ? 0.5 : 0.0)
-       : i == 3 ? (j == 1 ? 11.0 / 18.0 : j == 2 ? 1.0 / 18.0 : 0.0)
-       : i == 4 ? (j == 1 ? 5.0 / 6.0 : j == 2 ? -5.0 / 6.0 : j == 3 ? 0.5 : 0.0)
-       : i == 5 ? (j == 1 ? 0.25 : j == 2 ? 1.75 : j == 3 ? 0.75 : j == 4 ? -1.75 : 0.0)
-                : 0.0;
-}
-__host__ __device__ constexpr double ars_at(int i, int j) {  // implicit part, j < i
-  return i == 3 ? (j == 2 ? 1.0 / 6.0 : 0.0)
-       : i == 4 ? (j == 2 ? -0.5 : j == 3 ? 0.5 : 0.0)
-       : i == 5 ? (j == 2 ? 1.5 : j == 3 ? -1.5 : j == 4 ? 0.5 : 0.0)
-                : 0.0;
-}
-
+// IMEX Runge-Kutta stages (the ARS pairs of Ascher, Ruuth & Spiteri 1997; the
+// paper steps with ARS(4,4,3), its RK443, Section 4): stage i = 1..s+1 at
+// time t + c_i dt solves
+//   X_i = b_n + dt sum_{j<i} (a_ij N(X_j) + at_ij L X_j) + dt g L X_i,
+// L = -|k|^2/Rm; the pairs are stiffly accurate, so b_{n+1} = X_{s+1}.  The
+// stage sums R_i (i = 2..s+1) collect the j < i terms as the stages go;
+// X_i = R_i / (1 - dt g L).  The tableau comes in the Problem.
 __device__ __forceinline__ cplx cdivr(cplx a, double d) { return {a.re / d, a.im / d}; }
 
-// End of stage JS (1..4) for one mode of one component: X_JS from the
-// state (JS = 1) or its stage sum, the contributions of stage JS to the
-// later stage sums, and X_{JS+1}; after stage 4, X_5 is the new state.
+// End of stage JS for one mode of one component: X_JS from the state
+// (JS = 1) or its stage sum, the contributions of stage JS to the later stage
+// sums, and X_{JS+1}; after the last explicit stage, X_{s+1} is the new state.
 template <int JS>
 __device__ __forceinline__ cplx rk_update(cplx nl, double L, double d, double dt, size_t idx,
-                                          size_t rs, cplx* __restrict__ B, cplx* __restrict__ R) {
+                                          size_t rs, cplx* __restrict__ B, cplx* __restrict__ R,
+                                          const Problem& pb) {
+  const int S = pb.rk_s;
   const cplx X = JS == 1 ? B[idx] : cdivr(R[(JS - 2) * rs + idx], d);
   cplx next = czero();
 #pragma unroll
   for (int i = JS + 1; i <= 5; ++i) {
-    const double a = ars_a(i, JS), atl = ars_at(i, JS) * L;
+    if (i > S + 1) break;
+    const double a = pb.rk_a[i - 1][JS - 1], atl = pb.rk_at[i - 1][JS - 1] * L;
     const cplx base = JS == 1 ? X : R[(i - 2) * rs + idx];
     const cplx term = {a * nl.re + atl * X.re, a * nl.im + atl * X.im};
     const cplx Ri = cadd(base, cscale(term, dt));
     if (i == JS + 1) next = cdivr(Ri, d);
-    if (i == 5 && JS == 4) B[idx] = next;
+    if (i == S + 1 && JS == S) B[idx] = next;
     else R[(i - 2) * rs + idx] = Ri;
   }
   return next;
@@ -124,7 +111,7 @@ __device__ __forceinline__ cplx rk_update(cplx nl, double L, double d, double dt
 // inside a wavefront; no workgroup barrier.
 // mode 0: start of a slice (inverse transform of the state only);
 // mode 1: SBDF1 update; mode 2: SBDF2 update; RKS = j > 0 (mode ROW_RK + j):
-// end of ARS(4,4,3) stage j (stage sums in R).  last: skip the inverse.
+// end of Runge-Kutta stage j (stage sums in R).  last: skip the inverse.
 template <int N, int E, int RKS = 0>
 __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cplx* __restrict__ B,
                                           cplx* __restrict__ H, const cplx* __restrict__ T2,
@@ -168,12 +155,12 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
         nl[2] = mul_i<1>(csub(cscale(ey, dkx), cscale(ex, dky)));
         if constexpr (RKS > 0) {
           const double L = -(dkx * dkx + dky * dky + kz * kz) / pb.Rm;
-          const double d = 1.0 - dt * 0.5 * L;
+          const double d = 1.0 - dt * pb.rk_g * L;
           const size_t rs = (size_t)3 * M * M;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const size_t idx = (size_t)(c * M + r) * M + kx + K;
-            w[c][e] = rk_update<RKS>(nl[c], L, d, dt, idx, rs, B, R);
+            w[c][e] = rk_update<RKS>(nl[c], L, d, dt, idx, rs, B, R, pb);
           }
         } else {
           const double a = dt * (dkx * dkx + dky * dky + kz * kz) / pb.Rm;
@@ -369,7 +356,7 @@ __attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb
   const size_t rows = (size_t)3 * G::M * N;
   // SBDF steps at t0 + step dt; Runge-Kutta stage `stage` at t0 + step dt + c dt
   const double t = stage == 0 ? fb.t0[f] + step * pb.dt
-                              : fb.t0[f] + step * pb.dt + ars_c(stage) * pb.dt;
+                              : fb.t0[f] + step * pb.dt + pb.rk_c[stage - 1] * pb.dt;
   const FlowPhase fp = flow_phase(pb, t);
   col_tile<N, E, TX * G::T, E == 8 ? 8 : 4>(blockIdx.x * TX, tile, fb.T1 + f * rows,
                                             fb.T2 + f * rows, fb.tw, fp);
@@ -408,13 +395,14 @@ __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* 
     row_phase<N, ER>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1, tw, pb, 0,
                      false);
   __syncthreads();
-  if constexpr (RK) {  // ARS(4,4,3): four stages a step
+  if constexpr (RK) {  // IMEX Runge-Kutta: pb.rk_s stages a step
     for (int step = 0; step < nsteps; ++step) {
       auto stage = [&](auto js_c) {
         constexpr int js = decltype(js_c)::value;
-        const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt + ars_c(js) * pb.dt);
+        if (js > pb.rk_s) return;
+        const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt + pb.rk_c[js - 1] * pb.dt);
         for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
-        const bool last = step == nsteps - 1 && js == 4;
+        const bool last = step == nsteps - 1 && js == pb.rk_s;
         for (int r0 = 0; r0 < M; r0 += NGR)
           row_phase<N, ER, js>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1,
                                tw, pb, ROW_RK + js, last, R);
@@ -1165,12 +1153,12 @@ template <int N>
 static hipError_t propagate_multi(const FieldBatch& fb, const Problem& pb, int nfields,
                                   int nsteps, hipStream_t st) {
   hipError_t e = launch_rows<N>(fb, pb, nfields, 0, 0, st);
-  if (pb.scheme == 1) {  // ARS(4,4,3): one column and one row launch a stage
+  if (pb.scheme == 1) {  // Runge-Kutta: one column and one row launch a stage
     for (int s = 0; s < nsteps && e == hipSuccess; ++s)
-      for (int j = 1; j <= 4 && e == hipSuccess; ++j) {
+      for (int j = 1; j <= pb.rk_s && e == hipSuccess; ++j) {
         e = launch_cols<N>(fb, pb, nfields, s, st, j);
         if (e == hipSuccess)
-          e = launch_rows<N>(fb, pb, nfields, ROW_RK + j, s == nsteps - 1 && j == 4, st);
+          e = launch_rows<N>(fb, pb, nfields, ROW_RK + j, s == nsteps - 1 && j == pb.rk_s, st);
       }
     return e;
   }
@@ -1232,7 +1220,8 @@ hipError_t propagate2(int N, const FieldBatch& fb, const Problem& pb, int nfield
 hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                      int path, hipStream_t st) {
   if (nfields <= 0 || nsteps <= 0) return hipSuccess;
-  if (pb.scheme == 1 && fb.R == nullptr) return hipErrorInvalidValue;  // stage sums needed
+  if (pb.scheme == 1 && (fb.R == nullptr || pb.rk_s < 1 || pb.rk_s > 4))
+    return hipErrorInvalidValue;  // stage sums and a tableau needed
   if (path == PATH_SINGLE_WG) {
 #define CALL(n) launch_slice<n>(fb, pb, nfields, nsteps, st)
     switch (N) {
@@ -1311,7 +1300,8 @@ hipError_t sweep_conv_jobs(const SweepJob* d_jobs, int njobs, bool lds_resident,
 }
 
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
-  if (pb.scheme == 1 && a.Rc == nullptr) return hipErrorInvalidValue;  // stage sums needed
+  if (pb.scheme == 1 && (a.Rc == nullptr || pb.rk_s < 1 || pb.rk_s > 4))
+    return hipErrorInvalidValue;  // stage sums and a tableau needed
   switch (Nc) {
     case 16: return launch_sweep<16>(a, pb, st);
     case 32: return launch_sweep<32>(a, pb, st);

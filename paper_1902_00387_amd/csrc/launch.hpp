@@ -20,7 +20,16 @@ struct Problem {
   double dt;   // step size
   double amp;  // flow amplitude: 0 (none), 1 (Roberts), sqrt(3/2) (GP)
   int tdep;    // 1: Galloway-Proctor phases (cos t, sin t); 0: steady
-  int scheme = 0;  // 0: SBDF1-started SBDF2; 1: ARS(4,4,3) IMEX Runge-Kutta
+  int scheme = 0;  // 0: SBDF1-started SBDF2; 1: IMEX Runge-Kutta (tableau below)
+  // IMEX Runge-Kutta pair with rk_s explicit stages (1, 2 or 4), stiffly
+  // accurate: stage i = 1..rk_s+1 at t + rk_c[i-1] dt uses rk_a[i-1][j-1]
+  // (explicit) and rk_at[i-1][j-1] (implicit) for j < i and the implicit
+  // diagonal rk_g; the new state is stage rk_s + 1
+  int rk_s = 0;
+  double rk_g = 0.0;
+  double rk_c[4] = {0.0, 0.0, 0.0, 0.0};
+  double rk_a[5][4] = {};
+  double rk_at[5][4] = {};
 };
 
 // A batch of fields stepped together (all of grid size N).

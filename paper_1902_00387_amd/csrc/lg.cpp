@@ -301,7 +301,7 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
       fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
       fb.t0 = c->t0s.as<double>() + n0;
       fb.tw = c->tw.as<cplx>();
-      if (c->scheme_f == PD_SCHEME_RK443) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
+      if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
       PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
       sa.n0 = n0;
       sa.mode = 1;

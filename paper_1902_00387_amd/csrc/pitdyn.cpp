@@ -49,13 +49,42 @@ pd::Problem make_problem(const pd_ctx* c, double dt, int scheme) {
   pb.dt = dt;
   pb.amp = c->flow == PD_FLOW_NONE ? 0.0 : (c->flow == PD_FLOW_ROBERTS ? 1.0 : std::sqrt(1.5));
   pb.tdep = c->flow == PD_FLOW_GP ? 1 : 0;
-  pb.scheme = scheme == PD_SCHEME_RK443 ? 1 : 0;
+  pb.scheme = scheme == PD_SCHEME_SBDF2 ? 0 : 1;
+  // IMEX Runge-Kutta tableaus of Ascher, Ruuth & Spiteri (1997): rows are the
+  // stages 2..s+1, columns the stages 1..s they use
+  if (scheme == PD_SCHEME_RK443) {  // ARS(4,4,3)
+    const double c[4] = {0.0, 0.5, 2.0 / 3.0, 0.5};
+    const double a[5][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {11.0 / 18.0, 1.0 / 18.0, 0, 0},
+                            {5.0 / 6.0, -5.0 / 6.0, 0.5, 0}, {0.25, 1.75, 0.75, -1.75}};
+    const double at[5][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 1.0 / 6.0, 0, 0},
+                             {0, -0.5, 0.5, 0}, {0, 1.5, -1.5, 0.5}};
+    pb.rk_s = 4;
+    pb.rk_g = 0.5;
+    std::memcpy(pb.rk_c, c, sizeof c);
+    std::memcpy(pb.rk_a, a, sizeof a);
+    std::memcpy(pb.rk_at, at, sizeof at);
+  } else if (scheme == PD_SCHEME_RK222) {  // ARS(2,2,2)
+    const double g = 1.0 - 1.0 / std::sqrt(2.0), dl = 1.0 - 1.0 / (2.0 * g);
+    pb.rk_s = 2;
+    pb.rk_g = g;
+    pb.rk_c[0] = 0.0;
+    pb.rk_c[1] = g;
+    pb.rk_a[1][0] = g;
+    pb.rk_a[2][0] = dl;
+    pb.rk_a[2][1] = 1.0 - dl;
+    pb.rk_at[2][1] = 1.0 - g;
+  } else if (scheme == PD_SCHEME_RK111) {  // ARS(1,1,1), forward-backward Euler
+    pb.rk_s = 1;
+    pb.rk_g = 1.0;
+    pb.rk_c[0] = 0.0;
+    pb.rk_a[1][0] = 1.0;
+  }
   return pb;
 }
 
 // the convolution form of the coarse sweep steps SBDF2 only
 bool use_conv_sweep(const pd_ctx* c) {
-  if (c->coarse_form == PD_COARSE_FFT || c->scheme_c == PD_SCHEME_RK443) return false;
+  if (c->coarse_form == PD_COARSE_FFT || c->scheme_c != PD_SCHEME_SBDF2) return false;
   return c->Nc <= 64;
 }
 
@@ -63,9 +92,9 @@ bool use_conv_sweep(const pd_ctx* c) {
 // coarse sweep (none for SBDF2)
 pd_status ensure_rk_buffers(pd_ctx* c) {
   if (!c->have_time) return PD_OK;
-  if (c->scheme_f == PD_SCHEME_RK443)
+  if (c->scheme_f != PD_SCHEME_SBDF2)
     PD_HIP(c, c->Rf.ensure((size_t)4 * c->box_elems() * c->P * sizeof(cplx)), "alloc");
-  if (c->scheme_c == PD_SCHEME_RK443)
+  if (c->scheme_c != PD_SCHEME_SBDF2)
     PD_HIP(c, c->Rc.ensure((size_t)4 * 3 * c->Mc * c->Mc * sizeof(cplx)), "alloc");
   return PD_OK;
 }
@@ -142,7 +171,7 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
   fb.T2 = c->wT2.as<cplx>();
   fb.t0 = c->wt0.as<double>();
   fb.tw = twb->as<cplx>();
-  if (scheme == PD_SCHEME_RK443) {
+  if (scheme != PD_SCHEME_SBDF2) {
     PD_HIP(c, c->wR.ensure(4 * box * batch * sizeof(cplx)), "alloc");
     fb.R = c->wR.as<cplx>();
   }
@@ -249,8 +278,8 @@ pd_status pd_set_scheme(pd_ctx* c, pd_scheme fine, pd_scheme coarse) {
   if (!c) return PD_EINVAL;
   c->err.clear();
   for (int v : {(int)fine, (int)coarse})
-    if (v != PD_SCHEME_SBDF2 && v != PD_SCHEME_RK443) return fail(c, PD_EINVAL, "unknown scheme %d", v);
-  if (coarse == PD_SCHEME_RK443 && c->coarse_form == PD_COARSE_CONV)
+    if (v < PD_SCHEME_SBDF2 || v > PD_SCHEME_RK111) return fail(c, PD_EINVAL, "unknown scheme %d", v);
+  if (coarse != PD_SCHEME_SBDF2 && c->coarse_form == PD_COARSE_CONV)
     return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
   c->scheme_f = fine;
   c->scheme_c = coarse;
@@ -262,7 +291,7 @@ pd_status pd_set_coarse_form(pd_ctx* c, pd_coarse_form f) {
   if (!c) return PD_EINVAL;
   if (f != PD_COARSE_AUTO && f != PD_COARSE_FFT && f != PD_COARSE_CONV)
     return fail(c, PD_EINVAL, "unknown coarse form %d", (int)f);
-  if (f == PD_COARSE_CONV && c->scheme_c == PD_SCHEME_RK443)
+  if (f == PD_COARSE_CONV && c->scheme_c != PD_SCHEME_SBDF2)
     return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
   if (f == PD_COARSE_CONV && c->have_time && c->Nc > 64)
     return fail(c, PD_EINVAL, "the convolution coarse sweep needs N_coarse <= 64");
@@ -521,7 +550,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
     fb.t0 = c->t0s.as<double>() + n0;
     fb.tw = c->tw.as<cplx>();
-    if (c->scheme_f == PD_SCHEME_RK443) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
+    if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
     PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
     PD_HIP(c, hipEventRecord(ev[1], st), "event");
     // serial coarse sweep with the correction, then the defect sums

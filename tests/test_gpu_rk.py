@@ -1,7 +1,8 @@
-"""GPU parity of the ARS(4,4,3) IMEX Runge-Kutta stepper (the paper's RK443)
-against the FP64 oracle: steps on every grid, both flows, both launch paths;
-F and G over a slice with coarsening; Parareal with Runge-Kutta F and G;
-bitwise finite termination; argument errors.  Bar: relative L2 <= 1e-12."""
+"""GPU parity of the IMEX Runge-Kutta steppers -- ARS(4,4,3) (the paper's
+RK443), ARS(2,2,2), ARS(1,1,1) -- against the FP64 oracle: steps on every
+grid, both flows, both launch paths; F and G over a slice with coarsening;
+Parareal with Runge-Kutta F and G; bitwise finite termination; argument
+errors.  Bar: relative L2 <= 1e-12."""
 import numpy as np
 import pytest
 
@@ -36,21 +37,22 @@ def ctx(lib):
     c.close()
 
 
+@pytest.mark.parametrize("scheme", ["rk443", "rk222", "rk111"])
 @pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("flow", ["roberts", "gp"])
 @pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512])
-def test_rk443_steps_match_oracle(ctx, N, flow, path):
+def test_rk_steps_match_oracle(ctx, N, flow, path, scheme):
     kz, Rm, dt, batch = 0.57, 30.0, 4e-3, 3
     nsteps = 2 if N <= 256 else 1
     x = rand_box(N, 7 * N + path, batch)
     t0 = np.array([0.0, 1.7, 5.3])
     ctx.set_problem(flow, Rm, kz, N)
-    ctx.set_scheme("rk443", "rk443")
+    ctx.set_scheme(scheme, scheme)
     ctx.set_path(path)
-    print(f"rk443 steps N={N} flow={flow} path={path}", flush=True)
+    print(f"{scheme} steps N={N} flow={flow} path={path}", flush=True)
     y = ctx.steps(t0, dt, nsteps, dev(x)).cpu().numpy()
     for f in range(batch):
-        ref = stepper.propagate_rk443(x[f], flow, Rm, kz, t0[f], dt, nsteps)
+        ref = stepper.propagate_imex_rk(x[f], flow, Rm, kz, t0[f], dt, nsteps, scheme)
         assert rel(y[f], ref) <= TOL, (f, rel(y[f], ref))
 
 
@@ -71,7 +73,8 @@ def test_rk443_fine_and_coarse_slice(ctx, Nc):
         assert rel(yg[f], G(x[f], t0[f])) <= TOL
 
 
-@pytest.mark.parametrize("schemes", [("rk443", "rk443"), ("rk443", "sbdf2"), ("sbdf2", "rk443")])
+@pytest.mark.parametrize("schemes", [("rk443", "rk443"), ("rk443", "sbdf2"), ("sbdf2", "rk443"),
+                                     ("rk222", "rk111")])
 def test_rk443_parareal_matches_oracle(ctx, schemes):
     """Galloway-Proctor, Rm = 50, 32^2, T = 2 over 8 slices, fine dt = 5e-3,
     coarse dt = 5e-2 on 16^2 (FFT form of the coarse sweep for a Runge-Kutta
@@ -124,4 +127,4 @@ def test_rk443_scheme_errors(ctx, lib):
     ctx.set_scheme("sbdf2", "rk443")
     with pytest.raises(lib.PitdynError):
         ctx.set_coarse_form(2)
-    assert lib.lib.pd_set_scheme(ctx._h, 2, 0) == lib.EINVAL
+    assert lib.lib.pd_set_scheme(ctx._h, 4, 0) == lib.EINVAL
