@@ -124,8 +124,13 @@ def measured_traffic(kernel_prefix):
         return None
     if d.get("kernels_sha256_16") != kernels_digest():
         return None
+    # kernel_prefix names the leading template arguments, e.g. pd::k_rows<128,4,1>
+    # for the instantiation pd::k_rows<128, 4, 1, 0>
+    key = kernel_prefix.replace(" ", "").rstrip(">")
     for name, v in d["kernels"].items():
-        if name.split("(")[0].replace(" ", "").endswith(kernel_prefix.replace(" ", "")):
+        full = name.split("(")[0].replace(" ", "")
+        full = full[4:] if full.startswith("void") else full
+        if full.startswith(key) and full[len(key):len(key) + 1] in (",", ">"):
             return v["fetch_bytes"] + v["write_bytes"]
     return None
 
