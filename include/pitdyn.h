@@ -75,12 +75,16 @@ typedef enum {
 } pd_path;
 
 typedef enum {
-  PD_COARSE_AUTO = 0,  /* convolution form when N_coarse <= 64, else FFT      */
-  PD_COARSE_FFT = 1,   /* same pseudo-spectral kernels as the fine propagator */
-  PD_COARSE_CONV = 2   /* explicit term as the exact spectral convolution with
+  PD_COARSE_AUTO = 0,  /* convolution form for SBDF2 with N_coarse <= 64, else
+                          the multi-launch form                              */
+  PD_COARSE_FFT = 1,   /* same pseudo-spectral kernels as the fine propagator,
+                          the whole sweep in one workgroup                   */
+  PD_COARSE_CONV = 2,  /* explicit term as the exact spectral convolution with
                           the flow's four Fourier modes (|k| = 1); equals the
                           pseudo-spectral value to rounding since nothing
                           aliases on the 2/3 box; N_coarse <= 64             */
+  PD_COARSE_MULTI = 3  /* host-driven: per slice the multi-launch fine-step
+                          kernels on the coarse grid (batch of one)          */
 } pd_coarse_form;
 
 /* Time steppers (Section 4: IMEX, explicit advection and stretching, implicit

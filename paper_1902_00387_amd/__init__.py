@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(HERE, "libpitdyn.so")
 FLOW_NONE, FLOW_ROBERTS, FLOW_GP = 0, 1, 2
 FLOWS = {"none": FLOW_NONE, "roberts": FLOW_ROBERTS, "gp": FLOW_GP}
 PATH_AUTO, PATH_MULTI, PATH_SINGLE, PATH_MULTI2 = -1, 0, 1, 2
-COARSE_AUTO, COARSE_FFT, COARSE_CONV = 0, 1, 2
+COARSE_AUTO, COARSE_FFT, COARSE_CONV, COARSE_MULTI = 0, 1, 2, 3
 MAX_ITER = 256
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ESTATE, EUNSTABLE = 0, 1, -1, -2, -3, -4, -5

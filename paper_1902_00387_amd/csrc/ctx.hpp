@@ -94,6 +94,7 @@ struct DeviceGuard {
 pd::Problem make_problem(const pd_ctx* c, double dt, int scheme = PD_SCHEME_SBDF2);
 pd_status ensure_rk_buffers(pd_ctx* c);
 bool use_conv_sweep(const pd_ctx* c);
+hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgs& sa, const pd::Problem& pc, hipStream_t st);
 int choose_path(const pd_ctx* c, int nfields);
 hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
                       int nsteps, hipStream_t st);

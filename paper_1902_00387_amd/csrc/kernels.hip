@@ -939,6 +939,34 @@ __global__ __launch_bounds__(256) void k_gather(const cplx* __restrict__ U, cplx
     dst[i] = src[i];
 }
 
+// Multi-launch coarse sweep pieces: restriction of a compact fine box to the
+// compact coarse box (its central block), and the Parareal update of one
+// slice from the coarse result (zero-padded prolongation):
+//   mode 0: U_{n+1} = g,  mode 1: U_{n+1} = F_n + (g - Gold_n);  Gold_n = g.
+__global__ __launch_bounds__(256) void k_box_restrict(const cplx* __restrict__ Un,
+                                                      cplx* __restrict__ Bc, int M, int Mc) {
+  const int K = (M - 1) / 2, Kc = (Mc - 1) / 2;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < 3 * Mc * Mc; i += gridDim.x * 256) {
+    const int c = i / (Mc * Mc), rr = (i / Mc) % Mc, cc = i % Mc;
+    Bc[i] = Un[(c * M + rr + K - Kc) * M + cc + K - Kc];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_box_correct(const cplx* __restrict__ Bc,
+                                                     const cplx* __restrict__ Fn,
+                                                     cplx* __restrict__ Go, cplx* __restrict__ Un1,
+                                                     int M, int Mc, int mode) {
+  const int K = (M - 1) / 2, Kc = (Mc - 1) / 2;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < 3 * M * M; i += gridDim.x * 256) {
+    const int c = i / (M * M), r = (i / M) % M, cc = i % M;
+    const int dr = r - K, dc = cc - K;
+    cplx g = czero();
+    if (dr >= -Kc && dr <= Kc && dc >= -Kc && dc <= Kc) g = Bc[(c * Mc + dr + Kc) * Mc + dc + Kc];
+    Un1[i] = mode == 0 ? g : cadd(Fn[i], csub(g, Go[i]));
+    Go[i] = g;
+  }
+}
+
 // per-field squared two-norm, fixed-order reduction (one workgroup a field)
 __global__ __launch_bounds__(256) void k_norm2(const cplx* __restrict__ x, size_t len,
                                                double* out) {
@@ -1311,6 +1339,31 @@ hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) 
     case 512: return launch_sweep<512>(a, pb, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t sweep_multi(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
+  if (pb.scheme == 1 && (a.Rc == nullptr || pb.rk_s < 1 || pb.rk_s > 4)) return hipErrorInvalidValue;
+  if (a.t0s == nullptr) return hipErrorInvalidValue;
+  const int Mc = 2 * ((Nc - 1) / 3) + 1;
+  const size_t fbox = (size_t)3 * a.M * a.M;
+  const int gb = (int)((3 * Mc * Mc + 255) / 256), gf = (int)((fbox + 255) / 256);
+  FieldBatch fb;
+  fb.B = a.Bc;
+  fb.H = a.Hc;
+  fb.T1 = a.T1c;
+  fb.T2 = a.T2c;
+  fb.tw = a.twc;
+  fb.R = a.Rc;
+  for (int n = a.n0; n < a.P; ++n) {
+    hipLaunchKernelGGL(k_box_restrict, dim3(gb < 1024 ? gb : 1024), dim3(256), 0, st,
+                       a.U + n * fbox, a.Bc, a.M, Mc);
+    fb.t0 = a.t0s + n;
+    hipError_t e = propagate(Nc, fb, pb, 1, a.nsteps, PATH_MULTI, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_box_correct, dim3(gf < 1024 ? gf : 1024), dim3(256), 0, st, a.Bc,
+                       a.Fo + n * fbox, a.Gold + n * fbox, a.U + (n + 1) * fbox, a.M, Mc, a.mode);
+  }
+  return hipGetLastError();
 }
 
 static int grid_for(size_t total) {

@@ -59,6 +59,7 @@ struct SweepArgs {
   const cplx* Uprev = nullptr;  // [3][M][M] U^{k-1}_P (defect; the batched sweep fills it)
   cplx *Bc = nullptr, *Hc = nullptr, *T1c = nullptr, *T2c = nullptr;  // coarse workspaces
   cplx* Rc = nullptr;           // [4][3][Mc][Mc] coarse Runge-Kutta stage sums (scheme 1)
+  const double* t0s = nullptr;  // [P] slice start times (multi-launch sweep only)
   const cplx* twc = nullptr;    // coarse twiddles
   double* red = nullptr;        // [2] defect sums (may be null)
   const double* ftab = nullptr; // [P][nsteps][4] cos(py), sin(py), cos(px), sin(px) of the
@@ -91,6 +92,10 @@ hipError_t cols(int N, const FieldBatch& fb, const Problem& pb, int nfields, int
 hipError_t propagate2(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                       hipStream_t st, hipStream_t st2, hipEvent_t* ev);
 hipError_t sweep(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
+// Host-driven coarse sweep: per slice a restriction kernel, the multi-launch
+// propagator on the coarse grid (one field; SBDF2 or Runge-Kutta) and the
+// Parareal update kernel; no defect sums (the caller reduces them)
+hipError_t sweep_multi(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
 // Launch-shape variants of the two phase kernels (kind 0: rows, 1: columns):
 // count, description (rows: values a lane, waves a workgroup; columns: values a
 // lane, columns a workgroup), process-wide selection and current choice.

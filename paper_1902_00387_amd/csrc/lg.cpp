@@ -116,10 +116,11 @@ hipError_t coarse_one(pd_ctx* c, const cplx* D, cplx* g, int n, hipStream_t st) 
   sa.P = 1;
   sa.n0 = 0;
   sa.nbase = n;
+  sa.t0s = c->t0s.as<double>() + n;
   sa.nsteps = c->nc;
   sa.mode = 0;
   const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c);
-  return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
+  return coarse_sweep(c, sa, pc, st);
 }
 
 }  // namespace
@@ -276,7 +277,7 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
     if (rs != PD_OK) return rs;
   }
   auto sweep = [&]() {
-    return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
+    return coarse_sweep(c, sa, pc, st);
   };
   // the inputs the coarse propagator sees: U^0_n in the initial run, then the
   // changes U^k_n - U^{k-1}_n of every later iteration (plain-G trajectory)

@@ -99,7 +99,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
                     pf = make_problem(c, c->dtf, c->scheme_f);
   auto sweep = [&]() -> hipError_t {
-    return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, cs) : pd::sweep(c->Nc, sa, pc, cs);
+    return coarse_sweep(c, sa, pc, cs);
   };
 
   // everything earlier on the caller's stream comes first

@@ -17,6 +17,7 @@
 #include "launch.hpp"
 #include "runtime.hpp"
 #include "ctx.hpp"
+#include "nn.hpp"
 
 using pd::cplx;
 
@@ -86,6 +87,21 @@ pd::Problem make_problem(const pd_ctx* c, double dt, int scheme) {
 bool use_conv_sweep(const pd_ctx* c) {
   if (c->coarse_form == PD_COARSE_FFT || c->scheme_c != PD_SCHEME_SBDF2) return false;
   return c->Nc <= 64;
+}
+
+// The serial coarse sweep in the form the context selects: the exact
+// convolution (SBDF2, N_C <= 64), the one-workgroup FFT form, or the
+// host-driven multi-launch form (then the defect sums run after it).
+hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgs& sa, const pd::Problem& pc, hipStream_t st) {
+  if (use_conv_sweep(c)) return pd::sweep_conv(c->Nc, sa, pc, st);
+  const bool multi = c->coarse_form == PD_COARSE_MULTI ||
+                     (c->coarse_form == PD_COARSE_AUTO);
+  if (!multi) return pd::sweep(c->Nc, sa, pc, st);
+  if (sa.t0s == nullptr) sa.t0s = c->t0s.as<double>() + sa.nbase;
+  hipError_t e = pd::sweep_multi(c->Nc, sa, pc, st);
+  if (e == hipSuccess && sa.mode != 0 && sa.red != nullptr)
+    e = pd::nn::defect(sa.U + (size_t)sa.P * c->box_elems(), sa.Uprev, c->box_elems(), sa.red, st);
+  return e;
 }
 
 // stage-sum buffers of the Runge-Kutta steppers for the slice arrays and the
@@ -289,7 +305,7 @@ pd_status pd_set_scheme(pd_ctx* c, pd_scheme fine, pd_scheme coarse) {
 
 pd_status pd_set_coarse_form(pd_ctx* c, pd_coarse_form f) {
   if (!c) return PD_EINVAL;
-  if (f != PD_COARSE_AUTO && f != PD_COARSE_FFT && f != PD_COARSE_CONV)
+  if (f != PD_COARSE_AUTO && f != PD_COARSE_FFT && f != PD_COARSE_CONV && f != PD_COARSE_MULTI)
     return fail(c, PD_EINVAL, "unknown coarse form %d", (int)f);
   if (f == PD_COARSE_CONV && c->scheme_c != PD_SCHEME_SBDF2)
     return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
@@ -517,7 +533,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   sa.mode = 0;
   PD_HIP(c, hipEventRecord(ev[0], st), "event");
   auto run_sweep = [&]() -> hipError_t {
-    return use_conv_sweep(c) ? pd::sweep_conv(c->Nc, sa, pc, st) : pd::sweep(c->Nc, sa, pc, st);
+    return coarse_sweep(c, sa, pc, st);
   };
   if (kres >= 0) {
     // nothing to do: the state of iteration kres was supplied

@@ -212,11 +212,12 @@ def test_invalid_arguments(ctx, lib):
     assert ctx.fine(np.zeros(0), empty).shape[0] == 0
 
 
-@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("form", [1, 2, 3])
 def test_parareal_coarse_forms_match_oracle(ctx, lib, form):
-    """The serial coarse sweep in pseudo-spectral (FFT) form and in exact
-    spectral-convolution form both reproduce the oracle's Parareal iterates
-    (Galloway-Proctor, 64^2 fine, 32^2 coarse, 6 slices, 2 iterations)."""
+    """The serial coarse sweep in one-workgroup pseudo-spectral (FFT) form,
+    in exact spectral-convolution form and in host-driven multi-launch form
+    reproduces the oracle's Parareal iterates (Galloway-Proctor, 64^2 fine,
+    32^2 coarse, 6 slices, 2 iterations)."""
     N, Nc, kz, Rm, T, P, dtf, dtc, iters = 64, 32, 0.57, 50.0, 1.5, 6, 5e-3, 2.5e-2, 2
     b0 = initial_field(N, kz, 77)
     ctx.set_problem("gp", Rm, kz, N)
