@@ -392,8 +392,6 @@ def run_nc_sweep(args):
     _log(f"# serial fine {serial_s:.3f} s, |b(T)| {np.linalg.norm(uT):.3e}")
     rows = []
     for nc in (N // 8, N // 4, N // 2, N):
-        if nc > 128:
-            continue  # one-workgroup coarse sweeps above 128^2 take minutes
         errs = {}
         for cand in (0.1, 0.05, 0.025, 0.0125, 0.00625, 0.003125):
             ctx.set_time(T, P, dtf, cand, nc)
