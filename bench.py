@@ -495,6 +495,12 @@ def run_work_precision(args):
                       "reference": "rk443 dt=1.25e-4", "rows": rows}), flush=True)
 
 
+# Table 1 rows also solved by Parareal: row -> (N_C, coarse dt); the paper's
+# N_C = 8 for GP Rm = 3 is below the smallest grid here, so that row coarsens
+# in time only
+PARAREAL_ROWS = {2: (16, 0.1), 3: (64, 2e-2)}
+
+
 def run_table1(args):
     """Growth rates of the paper's Table 1 parameter sets from serial fine
     solves on the GPU over t in [0, 50] (50 slices of length 1; growth =
@@ -530,10 +536,29 @@ def run_table1(args):
             if n % 10 == 9:
                 _log(f"# table1 row {i} ({flow} Rm={Rm}): slice {n + 1}/{P}, {time.perf_counter() - t0:.1f} s")
         g = _growth(norms, 1.0)
-        ctx.close()
-        out.append({"flow": flow, "Rm": Rm, "kz": kz, "N": N, "dt": dt, "scheme": scheme,
-                    "growth_rate": g, "paper": paper, "seconds": time.perf_counter() - t0})
+        serial_s = time.perf_counter() - t0
+        row = {"flow": flow, "Rm": Rm, "kz": kz, "N": N, "dt": dt, "scheme": scheme,
+               "growth_rate": g, "paper": paper, "seconds": serial_s}
         _log(f"# table1 row {i}: growth {g:.4f} (paper {paper})")
+        if i in PARAREAL_ROWS:
+            # the same solution by Parareal with the paper's coarse propagator
+            # (ARS(4,4,3) on N_C with step dt_c) and the library's growth rate
+            Nc, dtc = PARAREAL_ROWS[i]
+            ctx.set_time(T, P, dt, dtc, Nc)
+            ctx.set_scheme(scheme, "rk443")
+            ctx.set_initial(b0)
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            rep = ctx.parareal(1e-8, P + 1)
+            gp = ctx.growth_rate()
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - tp
+            row["parareal"] = {"N_coarse": Nc, "dt_coarse": dtc, "k_con": rep["k_con"],
+                               "growth_rate": gp, "seconds": tp, "speedup_vs_serial_gpu": serial_s / tp}
+            _log(f"# table1 row {i} Parareal (N_C={Nc}, dt_c={dtc}): k_con {rep['k_con']}, "
+                 f"growth {gp:.4f}, {tp:.2f} s vs serial {serial_s:.2f} s")
+        ctx.close()
+        out.append(row)
     print(json.dumps({"experiment": "Table 1 growth rates", "T": 50.0, "rows": out}), flush=True)
 
 
