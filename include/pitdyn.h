@@ -299,6 +299,12 @@ pd_status pd_lg_set_params(pd_ctx* ctx, const float* in, size_t n);
 pd_status pd_lg_sample(pd_ctx* ctx, int i, float* x, float* r, double* t);
 /* Network output c[Q][6] on stored sample i. */
 pd_status pd_lg_forward_sample(pd_ctx* ctx, int i, float* out);
+/* Weight the training loss per box mode by w_m = exp(-beta |k_m|^2 dT / Rm),
+   the damping diffusion alone applies to mode m over beta slices, so that
+   the network spends its accuracy on the modes that persist from slice to
+   slice (loss = sum w |c - r|^2 / sum w |r|^2).  beta = 0 (the default):
+   uniform weights. */
+pd_status pd_lg_set_loss_decay(pd_ctx* ctx, double beta);
 /* Use the learned (1) or plain (0) coarse propagator in pd_parareal. */
 pd_status pd_set_coarse(pd_ctx* ctx, int learned);
 /* Save the network parameters to a file (8-byte magic "PDLGNET1", int32 N,

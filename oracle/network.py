@@ -91,13 +91,16 @@ def forward(params: dict, x: np.ndarray, t: np.ndarray, Mf: int):
     return h @ params["W_out"], cache
 
 
-def loss_and_grad(params: dict, x, t, r, Mf: int):
-    """Loss and gradients with respect to every parameter (manual backward)."""
+def loss_and_grad(params: dict, x, t, r, Mf: int, w=None):
+    """Loss sum w_m |c - r|^2 / sum w_m |r|^2 (per-mode weights w, [Q]; None:
+    all 1) and its gradients with respect to every parameter (manual
+    backward)."""
     c, cache = forward(params, x, t, Mf)
-    den = float(np.sum(r * r))
+    wm = np.ones(c.shape[1]) if w is None else np.asarray(w, dtype=np.float64)
     diff = c - r
-    loss = float(np.sum(diff * diff)) / den
-    dc = 2.0 * diff / den
+    den = float(np.sum(wm[None, :, None] * r * r))
+    loss = float(np.sum(wm[None, :, None] * diff * diff)) / den
+    dc = 2.0 * wm[None, :, None] * diff / den
     L = params["V"].shape[0]
     grads = {}
     hL = cache["hs"][-1]

@@ -43,7 +43,7 @@ SYMBOLS = [
     "pd_lg_init", "pd_lg_add_samples", "pd_lg_add_parareal_samples", "pd_lg_train", "pd_lg_loss", "pd_lg_gradients",
     "pd_lg_params", "pd_lg_set_params", "pd_lg_sample", "pd_lg_forward_sample", "pd_set_coarse",
     "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
-    "pd_lg_load", "pd_set_pipeline", "pd_set_scheme",
+    "pd_lg_load", "pd_set_pipeline", "pd_set_scheme", "pd_lg_set_loss_decay",
 ]
 
 
@@ -131,6 +131,7 @@ def _load():
         "pd_lg_load": ([vp, C.c_char_p], i),
         "pd_set_pipeline": ([vp, i, i], i),
         "pd_set_scheme": ([vp, i, i], i),
+        "pd_lg_set_loss_decay": ([vp, d], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -332,6 +333,10 @@ class Context:
     # -- learned coarse propagator -------------------------------------------
     def lg_init(self, layers: int = 4, seed: int = 0):
         self._ok(lib.pd_lg_init(self._h, int(layers), C.c_uint64(seed)))
+
+    def lg_set_loss_decay(self, beta: float):
+        """Per-mode loss weights exp(-beta |k|^2 dT / Rm) (0: uniform)."""
+        self._ok(lib.pd_lg_set_loss_decay(self._h, float(beta)))
 
     def lg_save(self, path: str):
         self._ok(lib.pd_lg_save(self._h, str(path).encode()))

@@ -62,6 +62,8 @@ struct pd_ctx {
     DevBuf act, ys, c, dc, dhA, dhB, dW, part, lpart, sums, bidx;
     int* hbidx = nullptr;              // pinned batch indices
     DevBuf Dn, gn, fn, nrm, uold;      // sweep and sample work (compact fine box)
+    DevBuf wq;                         // [Q] per-mode loss weights (empty: uniform)
+    bool weighted = false;
   } lg;
 
   size_t box_elems() const { return (size_t)3 * M * M; }

@@ -137,7 +137,8 @@ void lg_release(pd_ctx* c) {
   g.act.release(); g.ys.release(); g.c.release(); g.dc.release(); g.dhA.release();
   g.dhB.release(); g.dW.release(); g.part.release(); g.lpart.release(); g.sums.release();
   g.bidx.release(); g.Dn.release(); g.gn.release(); g.fn.release(); g.nrm.release();
-  g.uold.release();
+  g.uold.release(); g.wq.release();
+  g.weighted = false;
   g.init = g.enabled = false;
   g.S = 0;
   g.Bcap = 0;
@@ -389,7 +390,8 @@ static pd_status lg_pass(pd_ctx* c, const int* idx, int B, bool grad, double* su
   act_ptrs(c, B, h, y);
   PD_HIP(c, pd::nn::forward(net, g.xs.as<float>(), g.ts.as<double>(), g.bidx.as<int>(), B,
                             h.data(), y.data(), g.c.as<float>(), st), "forward");
-  PD_HIP(c, pd::nn::loss(g.c.as<float>(), g.rs.as<float>(), g.Q, B, g.bidx.as<int>(),
+  const float* wq = g.weighted ? g.wq.as<float>() : nullptr;
+  PD_HIP(c, pd::nn::loss(g.c.as<float>(), g.rs.as<float>(), g.Q, B, g.bidx.as<int>(), wq,
                          g.lpart.as<double>(), g.sums.as<double>(), st), "loss");
   if (grad) {
     pd::nn::Grads gr = net_of(c, g.grads);
@@ -399,6 +401,7 @@ static pd_status lg_pass(pd_ctx* c, const int* idx, int B, bool grad, double* su
     w.dhB = g.dhB.as<float>();
     w.dW = g.dW.as<float>();
     w.part = g.part.as<float>();
+    w.wq = wq;
     PD_HIP(c, pd::nn::backward(net, g.xs.as<float>(), g.ts.as<double>(), g.bidx.as<int>(), B,
                                h.data(), y.data(), g.c.as<float>(), g.rs.as<float>(),
                                g.sums.as<double>(), gr, w, st), "backward");
@@ -498,6 +501,33 @@ pd_status pd_lg_forward_sample(pd_ctx* c, int i, float* out) {
   pd_status s = lg_pass(c, &i, 1, false, sums);
   if (s != PD_OK) return s;
   PD_HIP(c, hipMemcpy(out, c->lg.c.p, sizeof(float) * c->lg.Q * 6, hipMemcpyDeviceToHost), "copy");
+  return PD_OK;
+}
+
+pd_status pd_lg_set_loss_decay(pd_ctx* c, double beta) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->lg.init) return fail(c, PD_ESTATE, "pd_lg_init not called");
+  if (!(beta >= 0) || !std::isfinite(beta)) return fail(c, PD_EINVAL, "beta must be finite and >= 0");
+  auto& g = c->lg;
+  if (beta == 0.0) {
+    g.weighted = false;
+    return PD_OK;
+  }
+  // w_m = exp(-beta |k_m|^2 dT / Rm): the factor by which diffusion alone
+  // damps mode m over beta slices
+  const int Mf = g.Mf, K = (Mf - 1) / 2;
+  std::vector<float> w((size_t)g.Q);
+  for (int r = 0; r < Mf; ++r)
+    for (int q = 0; q < Mf; ++q) {
+      const double ky = r - K, kx = q - K;
+      const double k2 = kx * kx + ky * ky + c->kz * c->kz;
+      w[(size_t)r * Mf + q] = (float)std::exp(-beta * k2 * c->dT / c->Rm);
+    }
+  DeviceGuard dg(c->device);
+  PD_HIP(c, g.wq.ensure(sizeof(float) * g.Q), "alloc");
+  PD_HIP(c, hipMemcpy(g.wq.p, w.data(), sizeof(float) * g.Q, hipMemcpyHostToDevice), "copy");
+  g.weighted = true;
   return PD_OK;
 }
 

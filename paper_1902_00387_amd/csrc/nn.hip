@@ -296,6 +296,7 @@ __global__ void k_sum_parts(const float* __restrict__ part, int nblk, int n,
 __global__ __launch_bounds__(256) void k_loss_part(const float* __restrict__ c,
                                                    const float* __restrict__ r, int Q, int B,
                                                    const int* __restrict__ bidx,
+                                                   const float* __restrict__ wq,
                                                    double* __restrict__ part) {
   __shared__ double red[2][256];
   const size_t total = (size_t)B * Q * 6;
@@ -304,9 +305,10 @@ __global__ __launch_bounds__(256) void k_loss_part(const float* __restrict__ c,
        i += (size_t)gridDim.x * blockDim.x) {
     const size_t b = i / ((size_t)Q * 6), rem = i - b * Q * 6;
     const size_t ri = (bidx ? (size_t)bidx[b] : b) * Q * 6 + rem;
+    const double wm = wq ? (double)wq[rem / 6] : 1.0;
     const double d = (double)c[i] - (double)r[ri];
-    s0 += d * d;
-    s1 += (double)r[ri] * (double)r[ri];
+    s0 += wm * d * d;
+    s1 += wm * (double)r[ri] * (double)r[ri];
   }
   red[0][threadIdx.x] = s0;
   red[1][threadIdx.x] = s1;
@@ -336,11 +338,11 @@ __global__ void k_loss_sum(const double* __restrict__ part, int nblk, double* __
   }
 }
 
-// dc = 2 (c - r) / sum r^2 ; then dh_L = dc W_out^T
+// dc = 2 w_m (c - r) / sum w r^2 ; then dh_L = dc W_out^T
 __global__ void k_dc_dh(const float* __restrict__ c, const float* __restrict__ r,
                         const double* __restrict__ sums, const float* __restrict__ Wout,
                         float* __restrict__ dc, float* __restrict__ dh, int Q, int B,
-                        const int* __restrict__ bidx) {
+                        const int* __restrict__ bidx, const float* __restrict__ wq) {
   const size_t total = (size_t)B * Q;
   const double den = sums[1];
   const float s2 = den > 0 ? (float)(2.0 / den) : 0.f;
@@ -348,10 +350,11 @@ __global__ void k_dc_dh(const float* __restrict__ c, const float* __restrict__ r
        i += (size_t)gridDim.x * blockDim.x) {
     const size_t b = i / Q, m = i - b * Q;
     const size_t ri = ((bidx ? (size_t)bidx[b] : b) * Q + m) * 6;
+    const float sw = wq ? s2 * wq[m] : s2;
     float d[6];
 #pragma unroll
     for (int o = 0; o < 6; ++o) {
-      d[o] = s2 * (c[i * 6 + o] - r[ri + o]);
+      d[o] = sw * (c[i * 6 + o] - r[ri + o]);
       dc[i * 6 + o] = d[o];
     }
 #pragma unroll 4
@@ -461,10 +464,10 @@ hipError_t forward(const Net& net, const float* x, const double* tb, const int* 
   return hipGetLastError();
 }
 
-hipError_t loss(const float* c, const float* r, int Q, int B, const int* bidx, double* part,
-                double* sums, hipStream_t st) {
+hipError_t loss(const float* c, const float* r, int Q, int B, const int* bidx, const float* wq,
+                double* part, double* sums, hipStream_t st) {
   const int nblk = 256;
-  hipLaunchKernelGGL(k_loss_part, dim3(nblk), dim3(256), 0, st, c, r, Q, B, bidx, part);
+  hipLaunchKernelGGL(k_loss_part, dim3(nblk), dim3(256), 0, st, c, r, Q, B, bidx, wq, part);
   hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, part, nblk, sums);
   return hipGetLastError();
 }
@@ -478,7 +481,7 @@ hipError_t backward(const Net& net, const float* x, const double* tb, const int*
   const int nblk = (int)((rows + rpb - 1) / rpb);
   // output layer
   hipLaunchKernelGGL(k_dc_dh, dim3(grid1(rows)), dim3(256), 0, st, c, r, sums, net.W_out, w.dc,
-                     w.dhA, Q, B, bidx);
+                     w.dhA, Q, B, bidx, w.wq);
   hipLaunchKernelGGL((k_outer<CH, 6>), dim3(nblk), dim3(256), 0, st, h[net.L], w.dc, w.part, Q,
                      B, nullptr, rpb);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, w.part, nblk, CH * 6, gr.W_out);

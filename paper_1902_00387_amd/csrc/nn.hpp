@@ -43,6 +43,7 @@ struct Work {
   float* dhB = nullptr;  // [B][Q][CH]
   float* dW = nullptr;   // [B][5][CH][CH]
   float* part = nullptr; // outer-product partials
+  const float* wq = nullptr;  // [Q] per-mode loss weights (null: all 1)
 };
 
 // x[b][m][12] = (re/im of D, re/im of g) / |D_b| from compact boxes [b][3][Q]
@@ -55,10 +56,11 @@ hipError_t targets(const cplx* F, const cplx* g, const double* nrm2, float* r, i
 // h[0..L], y[0..L-1]: [B][Q][CH] activations; c: [B][Q][6]
 hipError_t forward(const Net& net, const float* x, const double* tb, const int* bidx, int B,
                    float* const* h, float* const* y, float* c, hipStream_t st);
-// sums[0] = sum (c - r)^2, sums[1] = sum r^2 (r through bidx); part: >= 512 doubles
-hipError_t loss(const float* c, const float* r, int Q, int B, const int* bidx, double* part,
-                double* sums, hipStream_t st);
-// gradients of sums[0]/sums[1] with respect to every parameter
+// sums[0] = sum w_m (c - r)^2, sums[1] = sum w_m r^2 (r through bidx; w_m the
+// per-mode weight, all 1 when wq is null); part: >= 512 doubles
+hipError_t loss(const float* c, const float* r, int Q, int B, const int* bidx, const float* wq,
+                double* part, double* sums, hipStream_t st);
+// gradients of sums[0]/sums[1] with respect to every parameter (weights w.wq)
 hipError_t backward(const Net& net, const float* x, const double* tb, const int* bidx, int B,
                     float* const* h, float* const* y, const float* c, const float* r,
                     const double* sums, Grads& gr, Work& w, hipStream_t st);

@@ -45,9 +45,13 @@ def small_ctx(lib, N=32, P=4, layers=2, seed=1):
     return ctx
 
 
-def test_network_forward_and_gradients_match_fp64_reference(lib):
+@pytest.mark.parametrize("beta", [0.0, 4.0])
+def test_network_forward_and_gradients_match_fp64_reference(lib, beta):
+    """Forward and gradients of the loss (uniform, or weighted per mode by
+    exp(-beta |k|^2 dT / Rm)) against the FP64 reference network."""
     N, L = 32, 2
     with small_ctx(lib, N=N, layers=L) as ctx:
+        ctx.lg_set_loss_decay(beta)
         D = np.stack([initial_field(N, 0.57, 40 + i, amp=1.0, kmax=6) for i in range(4)])
         ctx.lg_add_samples(np.array([0.0, 0.25, 0.5, 0.75]), dev(D))
         rng = np.random.default_rng(0)
@@ -67,7 +71,11 @@ def test_network_forward_and_gradients_match_fp64_reference(lib):
             c_gpu = ctx.lg_forward_sample(i)
             assert relnorm(c_gpu, c_ref[i]) <= 1e-2, (i, relnorm(c_gpu, c_ref[i]))
         g_gpu, loss_gpu = ctx.lg_gradients(0, 4)
-        loss_ref, g_ref = onet.loss_and_grad(prm, x, t, r, Mf)
+        K = (N - 1) // 3
+        ky, kx = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+        dT, Rm, kz = 1.0 / 4, 50.0, 0.57
+        w = np.exp(-beta * (kx ** 2 + ky ** 2 + kz ** 2) * dT / Rm).ravel() if beta > 0 else None
+        loss_ref, g_ref = onet.loss_and_grad(prm, x, t, r, Mf, w)
         assert abs(loss_gpu - loss_ref) <= 1e-2 * loss_ref
         gg = unflatten(g_gpu, Q, L)
         for name in ("W_in", "V", "gamma", "W_out"):

@@ -17,19 +17,21 @@ def tiny(seed=0, Mf=5, C=4, L=2, B=2):
     return p, x, t, r, Mf
 
 
+@pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("name", ["W_in", "V", "gamma", "W_out"])
-def test_manual_gradients_match_central_differences(name):
+def test_manual_gradients_match_central_differences(name, weighted):
     p, x, t, r, Mf = tiny()
-    _, g = net.loss_and_grad(p, x, t, r, Mf)
+    w = np.random.default_rng(4).uniform(0.1, 2.0, Mf * Mf) if weighted else None
+    _, g = net.loss_and_grad(p, x, t, r, Mf, w)
     rng = np.random.default_rng(1)
     flat = p[name].reshape(-1)
     for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
         h = 1e-6
         old = flat[idx]
         flat[idx] = old + h
-        lp, _ = net.loss_and_grad(p, x, t, r, Mf)
+        lp, _ = net.loss_and_grad(p, x, t, r, Mf, w)
         flat[idx] = old - h
-        lm, _ = net.loss_and_grad(p, x, t, r, Mf)
+        lm, _ = net.loss_and_grad(p, x, t, r, Mf, w)
         flat[idx] = old
         fd = (lp - lm) / (2 * h)
         an = g[name].reshape(-1)[idx]
@@ -58,3 +60,18 @@ def test_learned_propagator_is_linear_and_zero_at_zero():
     assert np.allclose(b, 2.5 * a, rtol=1e-12, atol=1e-12)
     z = net.apply(p, 0 * D, 0 * g, t)
     assert np.all(z == 0)
+
+
+def test_weighted_loss_closed_form():
+    """With all weights equal the weighted loss is the plain one; with a
+    weight on one mode only it is that mode's relative error."""
+    p, x, t, r, Mf = tiny(seed=5)
+    l1, _ = net.loss_and_grad(p, x, t, r, Mf)
+    l2, _ = net.loss_and_grad(p, x, t, r, Mf, np.full(Mf * Mf, 3.0))
+    assert abs(l1 - l2) <= 1e-14 * l1
+    w = np.zeros(Mf * Mf)
+    w[7] = 1.0
+    c, _ = net.forward(p, x, t, Mf)
+    ref = np.sum((c[:, 7] - r[:, 7]) ** 2) / np.sum(r[:, 7] ** 2)
+    l3, _ = net.loss_and_grad(p, x, t, r, Mf, w)
+    assert abs(l3 - ref) <= 1e-14 * ref
