@@ -7,6 +7,22 @@ Fields are complex128 arrays ``[..., 3, N, N]`` of Fourier coefficients
 m - N), zero outside the 2/3 box |kx|, |ky| <= (N-1)//3.  See
 ``include/pitdyn.h`` for the C-ABI this wraps.
 
+Typical use (Galloway-Proctor dynamo, Rm = 100, 128^2, T = 64 over 64
+slices, fine SBDF2 dt = 2e-3, coarse 64^2 with dt = 1e-2)::
+
+    import paper_1902_00387_amd as pd
+    with pd.Context(0) as ctx:
+        ctx.set_problem("gp", 100.0, 0.57, 128)
+        ctx.set_time(64.0, 64, 2e-3, 1e-2, 64)
+        ctx.set_initial(b0)                  # [3, 128, 128] complex128
+        rep = ctx.parareal(1e-8, 65)         # k_con, sigma, timings
+        gamma = ctx.growth_rate()
+        U = ctx.get_slices()                 # [65, 3, 128, 128]
+
+``set_scheme("rk443", "rk443")`` selects the paper's Runge-Kutta stepper,
+``Batch`` runs many uneven instances at once, ``lg_*`` train and use the
+learned coarse propagator.
+
 Importing this package loads the library and raises if it is missing: there
 is no CPU fallback.  torch is imported first so that the process holds one
 HIP runtime (torch's): the library resolves ``libamdhip64.so.7`` to the copy
