@@ -179,9 +179,9 @@ pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int 
 pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
 
 /* Order of the work inside pd_parareal with the plain coarse propagator.
-   chunks >= 2 (default 3, speculate 2): pipelined -- the serial coarse sweep runs on a stream of its
+   chunks >= 2 (default 2, speculate 2): pipelined -- the serial coarse sweep runs on a stream of its
    own in `chunks` runs of consecutive slices, and the fine sweep of a run of
-   slices (on up to three fine streams) starts as soon as the coarse sweep has
+   slices (on one of two fine streams) starts as soon as the coarse sweep has
    produced its start values, so the fine sweeps of iteration k + 1 overlap
    the coarse sweep of iteration k.  They start before the defect of
    iteration k is known: speculate = 1 every run, 0 all but the last run,

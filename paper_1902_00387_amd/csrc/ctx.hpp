@@ -20,10 +20,8 @@ struct pd_ctx {
   hipEvent_t sev[3] = {nullptr, nullptr, nullptr};
   hipStream_t cst = nullptr;       // pipelined Parareal: coarse sweep stream
   hipStream_t fst = nullptr;       // pipelined Parareal: fine streams
-  hipStream_t fst2 = nullptr;
-  hipStream_t fst3 = nullptr;
   int pipe_spec = 2;               // pipelined: which chunks of the next fine sweep start early
-  int pipe_chunks = 3;             // slice chunks of the pipelined Parareal (< 2: off)
+  int pipe_chunks = 2;             // slice chunks of the pipelined Parareal (< 2: off)
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;

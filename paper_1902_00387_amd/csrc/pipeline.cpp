@@ -43,7 +43,7 @@ namespace pd {
 namespace ctxh {
 
 pd_status ensure_pipeline_streams(pd_ctx* c) {
-  for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2, &c->fst3})
+  for (hipStream_t* p : {&c->cst, &c->fst})
     if (!*p) PD_HIP(c, hipStreamCreateWithFlags(p, hipStreamNonBlocking), "stream");
   return PD_OK;
 }
@@ -62,10 +62,14 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   auto hi = [&](int ch) { return std::min(P, (ch + 1) * Sc); };
   cplx* U = c->U.as<cplx>();
   cplx* Fo = c->Fo.as<cplx>();
-  // up to three fine streams: a chunk's fine launches are latency-bound, so
-  // chunks must run side by side to keep the chip as busy as one full sweep
-  hipStream_t fs[3] = {c->fst, c->fst2, c->fst3};
-  const int NFS = std::min(C, 3);
+  // two fine streams, the context's own and one more: a chunk's fine launches
+  // are latency-bound, so chunks run side by side to keep the chip as busy as
+  // one full sweep.  HIP spreads a process's streams over a few hardware
+  // queues (four by default); more streams would share a queue and
+  // serialise, so the coarse stream, the two fine streams and the caller's
+  // default stream are all this schedule uses
+  hipStream_t fs[2] = {c->stream, c->fst};
+  const int NFS = std::min(C, 2);
   hipStream_t cs = c->cst;
 
   // per parity of the iteration and chunk: fine start, start values copied,
@@ -79,7 +83,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   auto Gs = [&](int k, int ch) { return ev(3, k, ch); };
   auto Ge = [&](int k, int ch) { return ev(4, k, ch); };
   hipEvent_t evIn = E.ev[10 * C], evRed = E.ev[10 * C + 1];
-  hipEvent_t evJoin[3] = {E.ev[10 * C + 2], E.ev[10 * C + 3], E.ev[10 * C + 4]};
+  hipEvent_t evJoin[2] = {E.ev[10 * C + 2], E.ev[10 * C + 3]};
 
   pd::SweepArgs sa;
   sa.U = U;

@@ -125,8 +125,12 @@ int choose_path(const pd_ctx* c, int nfields) {
 hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
                       int nsteps, hipStream_t st) {
   const int path = choose_path(c, nfields);
-  if (path == PD_PATH_MULTI2 && fb.map == nullptr)
+  if (path == PD_PATH_MULTI2 && fb.map == nullptr) {
+    // the second stream of the two-stream path exists only once it is used:
+    // HIP spreads a process's streams over a few hardware queues
+    if (c->side == nullptr && hipStreamCreate(&c->side) != hipSuccess) return hipErrorOutOfMemory;
     return pd::propagate2(c->N, fb, pb, nfields, nsteps, st, c->side, c->sev);
+  }
   return pd::propagate(c->N, fb, pb, nfields, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st);
 }
 
@@ -221,7 +225,7 @@ pd_status pd_create(pd_ctx** out, int hip_device) {
   if (!c) return PD_ENOMEM;
   c->device = hip_device;
   DeviceGuard dg(hip_device);
-  if (hipStreamCreate(&c->own) != hipSuccess || hipStreamCreate(&c->side) != hipSuccess ||
+  if (hipStreamCreate(&c->own) != hipSuccess ||
       hipEventCreateWithFlags(&c->sev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->sev[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->sev[2], hipEventDisableTiming) != hipSuccess ||
@@ -246,7 +250,7 @@ void pd_destroy(pd_ctx* c) {
       (void)hipStreamSynchronize(c->side);
       (void)hipStreamDestroy(c->side);
     }
-    for (hipStream_t* p : {&c->cst, &c->fst, &c->fst2, &c->fst3})
+    for (hipStream_t* p : {&c->cst, &c->fst})
       if (*p) {
         (void)hipStreamSynchronize(*p);
         (void)hipStreamDestroy(*p);
