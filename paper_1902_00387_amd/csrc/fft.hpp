@@ -7,7 +7,9 @@
 // (k < R), which for the strided layout are the lane's own registers, so a
 // pass needs no load exchange; its outputs go to LDS at their autosorted
 // positions and are read back in the strided layout for the next pass.  The
-// final read-back leaves the transform in natural order, again strided.
+// last pass's outputs already sit in the lane's own strided registers, so it
+// runs in place without LDS and leaves the transform in natural order,
+// strided: a transform of P passes makes P - 1 LDS exchanges.
 //
 // DIR = -1 is the forward transform X_k = sum_n x_n e^{-2 pi i nk/N},
 // DIR = +1 the unnormalised inverse.  Twiddles come from a table
@@ -161,10 +163,32 @@ struct TwRegs {
 // One Stockham pass of radix R over sub-transforms of length NS, E values a
 // lane.  Lane j owns butterflies b = j + T*q, q < E/R (T = N/E lanes); wl
 // holds its (E/R) * (R-1) twiddles of this pass.  Outputs are scattered to
-// LDS (padded), then the lane reads back its strided values.
+// LDS (padded), then the lane reads back its strided values.  In the last
+// pass (NS * R = N) output k of butterfly b lands at b + k*NS = j + T*(q +
+// Q*k), which is the lane's own strided register q + Q*k: the butterfly runs
+// in place in registers and the pass needs no exchange.
 template <int N, int E, int R, int NS, int DIR>
 __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* wl) {
   constexpr int T = N / E, Q = E / R;
+  if constexpr (NS * R == N) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      cplx x[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) x[k] = v[q + k * Q];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int k = 1; k < R; ++k) {
+          const cplx w = wl[q * (R - 1) + k - 1];
+          x[k] = (DIR < 0) ? cmul(x[k], w) : cmulc(x[k], w);
+        }
+      }
+      dftR<R, DIR>(x);
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[q + k * Q] = x[k];
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int b = j + T * q;
