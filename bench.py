@@ -184,14 +184,17 @@ def run_batch(args):
         b.add("gp", it["Rm"], it["kz"], it["N"], it["T"], it["P"], it["dtf"], it["dtc"], it["Nc"],
               initial_field(it["N"], it["kz"], it["seed"]))
     print(f"# batch: {len(inst)} instances", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     st = b.run(TOL, 33, use_graph=True)   # first run builds buffers and captures the graph
     torch.cuda.synchronize()
+    print(f"# batch: first run (graph capture) {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     times = []
-    for _ in range(max(1, args.steps)):
+    for i in range(max(1, args.steps)):
         t0 = time.perf_counter()
         st = b.run(TOL, 33, use_graph=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+        print(f"# batch: timed run {i + 1}: {times[-1]:.1f} s", file=sys.stderr, flush=True)
     secs = min(times)
     reps = [b.result(i) for i in range(len(inst))]
     done_ms = 0.0
