@@ -722,6 +722,9 @@ def main():
             "coarse_sweeps_s": rep["t_coarse_s"] + rep["t_coarse0_s"],
             "serial_fine_gpu_s": serial_s,
             "speedup_vs_serial_fine_gpu": serial_s / (ms_step * 1e-3),
+            # eq. speed_up from the report's per-stream sweep times (they
+            # overlap in the pipelined schedule, so R_f and R_c are overstated)
+            "Rf_over_Rc": rep["Rf_over_Rc"], "model_speedup": rep["model_speedup"],
         },
         "autotune": {"rows_variant": list(pd.variants(N, 0)[tuned[0]]),
                      "cols_variant": list(pd.variants(N, 1)[tuned[1]]),

@@ -107,6 +107,15 @@ typedef struct {
   double t_fine_s;             /* all fine sweeps (GPU time)               */
   double t_coarse_s;           /* all correction sweeps (GPU time)         */
   double t_total_s;            /* wall clock of the whole call             */
+  /* R_f / R_c and the speed-up estimate of eq. speed_up, from the times
+     above (Section 3.1): a fine sweep runs every slice at once, so its mean
+     time stands for R_f, one slice of F; a coarse sweep runs the slices one
+     after another, so its mean time over n_slices stands for R_c;
+     model_speedup = [(1 + k/P) R_c/R_f + k/P]^-1 with k = k_con (iters if
+     not converged).  Pipelined runs overlap their sweeps, so their summed
+     times overstate R_f and R_c.  0 when no sweep was timed. */
+  double Rf_over_Rc;
+  double model_speedup;
 } pd_report;
 
 /* Context on HIP device `hip_device` with its own stream. */

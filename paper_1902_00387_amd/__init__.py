@@ -72,6 +72,8 @@ class Report(C.Structure):
         ("t_fine_s", C.c_double),
         ("t_coarse_s", C.c_double),
         ("t_total_s", C.c_double),
+        ("Rf_over_Rc", C.c_double),
+        ("model_speedup", C.c_double),
     ]
 
     def as_dict(self):
@@ -80,6 +82,7 @@ class Report(C.Structure):
             "sigma": [self.sigma[i] for i in range(self.iters)],
             "t_coarse0_s": self.t_coarse0_s, "t_fine_s": self.t_fine_s,
             "t_coarse_s": self.t_coarse_s, "t_total_s": self.t_total_s,
+            "Rf_over_Rc": self.Rf_over_Rc, "model_speedup": self.model_speedup,
         }
 
 

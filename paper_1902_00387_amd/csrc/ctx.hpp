@@ -92,6 +92,8 @@ struct DeviceGuard {
 };
 
 pd::Problem make_problem(const pd_ctx* c, double dt, int scheme = PD_SCHEME_SBDF2);
+// fills the report's R_f / R_c and model speed-up from its sweep times
+void finish_report(pd_report& r, int P);
 pd_status ensure_rk_buffers(pd_ctx* c);
 bool use_conv_sweep(const pd_ctx* c);
 hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgs& sa, const pd::Problem& pc, hipStream_t st);

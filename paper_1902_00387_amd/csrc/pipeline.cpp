@@ -240,6 +240,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   PD_HIP(c, hipStreamWaitEvent(c->stream, evRed, 0), "wait");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
   r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  finish_report(r, P);
   if (rep) *rep = r;
   return status;
 }

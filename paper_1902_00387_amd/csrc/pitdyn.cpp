@@ -43,6 +43,21 @@ pd_status hipfail(pd_ctx* c, hipError_t e, const char* what) {
   return fail(c, PD_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+
+// Section 3.1, eq. speed_up: R_f from the mean fine sweep (all slices at
+// once), R_c from the mean coarse sweep over P (slices one after another).
+void finish_report(pd_report& r, int P) {
+  r.Rf_over_Rc = 0.0;
+  r.model_speedup = 0.0;
+  const int sweeps_c = r.iters + (r.t_coarse0_s > 0.0 ? 1 : 0);
+  const double tc = r.t_coarse0_s + r.t_coarse_s;
+  if (P < 1 || r.iters < 1 || r.t_fine_s <= 0.0 || sweeps_c < 1 || tc <= 0.0) return;
+  const double Rf = r.t_fine_s / r.iters, Rc = tc / sweeps_c / P;
+  r.Rf_over_Rc = Rf / Rc;
+  const double k = r.k_con > 0 ? r.k_con : r.iters;
+  r.model_speedup = 1.0 / ((1.0 + k / P) * (Rc / Rf) + k / P);
+}
+
 pd::Problem make_problem(const pd_ctx* c, double dt, int scheme) {
   pd::Problem pb;
   pb.Rm = c->Rm;
@@ -606,6 +621,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   }
   if (max_iter == 0) status = PD_OK;
   r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  finish_report(r, c->P);
   if (rep) *rep = r;
   return status;
 }

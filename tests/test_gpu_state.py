@@ -121,3 +121,27 @@ def test_learned_parameter_file_round_trip(lib, tmp_path):
             for bad in ("short.bin", "magic.bin", "missing.bin"):
                 with pytest.raises(lib.PitdynError):
                     c4.lg_load(tmp_path / bad)
+
+
+@pytest.mark.parametrize("chunks", [0, 2])
+def test_report_speedup_model_matches_its_times(lib, chunks):
+    """R_f / R_c and the speed-up estimate in the report follow eq. speed_up
+    from the report's own sweep times (oracle formula), stay under the
+    bound of eq. speed_bound, and are zero when no iteration ran."""
+    from oracle import parareal as pr
+    N, P, tol = 32, 6, 1e-10
+    with lib.Context(0) as ctx:
+        problem(ctx, N=N, P=P)
+        ctx.set_pipeline(chunks)
+        ctx.set_initial(initial_field(N, 0.57, 41))
+        r = ctx.parareal(tol, P + 1)
+        k = r["k_con"] if r["k_con"] > 0 else r["iters"]
+        Rf = r["t_fine_s"] / r["iters"]
+        Rc = (r["t_coarse0_s"] + r["t_coarse_s"]) / (r["iters"] + 1) / P
+        assert r["Rf_over_Rc"] == pytest.approx(Rf / Rc, rel=1e-12)
+        s = pr.speedup_model(k, P, Rc / Rf)
+        assert r["model_speedup"] == pytest.approx(s, rel=1e-12)
+        assert 0.0 < r["model_speedup"] <= pr.speedup_bound(k, P, Rc / Rf) * (1 + 1e-12)
+        ctx.set_initial(initial_field(N, 0.57, 41))
+        r0 = ctx.parareal(tol, 0)
+        assert r0["Rf_over_Rc"] == 0.0 and r0["model_speedup"] == 0.0
