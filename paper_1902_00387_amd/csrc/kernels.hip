@@ -553,6 +553,30 @@ constexpr int CONV_LANES = 1024;
 constexpr int CONV_MMAX = 45;  // coarse box width held in LDS (N_C <= 64)
 constexpr int CONV_MPL = (CONV_MMAX * CONV_MMAX + CONV_LANES - 1) / CONV_LANES;  // modes a lane
 
+// dt N = dt i k x E with (dkx, dky, dkz) = dt k: component c is
+// i (dk_{c+1} E_{c+2} - dk_{c+2} E_{c+1}).
+__device__ __forceinline__ void dt_curl(const cplx e[3], double dkx, double dky, double dkz,
+                                        cplx dn[3]) {
+  dn[0] = mul_i<1>(csub(cscale(e[2], dky), cscale(e[1], dkz)));
+  dn[1] = mul_i<1>(csub(cscale(e[0], dkz), cscale(e[2], dkx)));
+  dn[2] = mul_i<1>(csub(cscale(e[1], dkx), cscale(e[0], dky)));
+}
+
+// SBDF1 (step 0: b' = (b + dN) inv) or SBDF2 (b' = (2b + 2dN + h) inv) update
+// of one component from dN = dt N; h holds the previous step's -b/2 - dN on
+// entry and this step's on exit.  inv = 1 / (1 + dt|k|^2/Rm) or
+// 1 / (3/2 + dt|k|^2/Rm).
+__device__ __forceinline__ cplx sbdf_update(cplx b, cplx d, cplx& h, double inv, int step) {
+  cplx bn;
+  if (step == 0) {
+    bn = {(b.re + d.re) * inv, (b.im + d.im) * inv};
+  } else {
+    bn = {(2.0 * b.re + (2.0 * d.re + h.re)) * inv, (2.0 * b.im + (2.0 * d.im + h.im)) * inv};
+  }
+  h = {-0.5 * b.re - d.re, -0.5 * b.im - d.im};
+  return bn;
+}
+
 // One workgroup runs the coarse sweep; lane l owns box modes l + CONV_LANES*m
 // (state and history in registers) and reads neighbours from LDS.
 __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem& pb, int Mc,
@@ -562,15 +586,21 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
   const int M = a.M, K = (a.M - 1) / 2;
   const size_t fbox = (size_t)3 * M * M;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double kz = pb.kz, dt = pb.dt;
+  const double kz = pb.kz, dt = pb.dt, dkz = dt * kz;
   // owned modes
+  // owned modes and their implicit factors (SBDF1, SBDF2)
   int own[CONV_MPL], oky[CONV_MPL], okx[CONV_MPL];
+  double inv1[CONV_MPL], inv2[CONV_MPL];
 #pragma unroll
   for (int m = 0; m < CONV_MPL; ++m) {
     own[m] = tid + m * nt;
     const int i = own[m] < nbox ? own[m] : 0;
     oky[m] = i / Mc - Kc;
     okx[m] = i % Mc - Kc;
+    const double kxd = okx[m], kyd = oky[m];
+    const double aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / pb.Rm;
+    inv1[m] = 1.0 / (1.0 + aa);
+    inv2[m] = 1.0 / (1.5 + aa);
   }
   for (int n = a.n0; n < a.P; ++n) {
     const cplx* Un = a.U + n * fbox;
@@ -605,6 +635,8 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
         //  q = (-1,0), u = am (1, 0, +i): (-i am by,  i am bx - am bz,  am by)
         //  q = (0,+1), u = bp (0, -i, 1): (-i bp bz - bp by,  bp bx,  i bp bx)
         //  q = (0,-1), u = bm (0, +i, 1): ( i bm bz - bm by,  bm bx, -i bm bx)
+        // with the two-term entries taken as one product, e.g.
+        // -i ap bx - ap bz = -ap (i bx + bz): two complex products a neighbour
         cplx e[3] = {czero(), czero(), czero()};
         const int ky = oky[m], kx = okx[m];
         if (ky - 1 >= -Kc) {
@@ -612,7 +644,7 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx aby = cmul(fm.ap, by);
           e[0] = cadd(e[0], mul_i<1>(aby));
-          e[1] = csub(e[1], cadd(mul_i<1>(cmul(fm.ap, bx)), cmul(fm.ap, bz)));
+          e[1] = csub(e[1], cmul(fm.ap, cadd(mul_i<1>(bx), bz)));
           e[2] = cadd(e[2], aby);
         }
         if (ky + 1 <= Kc) {
@@ -620,14 +652,14 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx aby = cmul(fm.am, by);
           e[0] = csub(e[0], mul_i<1>(aby));
-          e[1] = cadd(e[1], csub(mul_i<1>(cmul(fm.am, bx)), cmul(fm.am, bz)));
+          e[1] = cadd(e[1], cmul(fm.am, csub(mul_i<1>(bx), bz)));
           e[2] = cadd(e[2], aby);
         }
         if (kx - 1 >= -Kc) {
           const int si = (ky + Kc) * Mc + kx - 1 + Kc;
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx bbx = cmul(fm.bp, bx);
-          e[0] = csub(e[0], cadd(mul_i<1>(cmul(fm.bp, bz)), cmul(fm.bp, by)));
+          e[0] = csub(e[0], cmul(fm.bp, cadd(mul_i<1>(bz), by)));
           e[1] = cadd(e[1], bbx);
           e[2] = cadd(e[2], mul_i<1>(bbx));
         }
@@ -635,27 +667,15 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
           const int si = (ky + Kc) * Mc + kx + 1 + Kc;
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx bbx = cmul(fm.bm, bx);
-          e[0] = cadd(e[0], csub(mul_i<1>(cmul(fm.bm, bz)), cmul(fm.bm, by)));
+          e[0] = cadd(e[0], cmul(fm.bm, csub(mul_i<1>(bz), by)));
           e[1] = cadd(e[1], bbx);
           e[2] = csub(e[2], mul_i<1>(bbx));
         }
-        const double kxd = kx, kyd = ky;
-        const double aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / pb.Rm;
-        cplx nl[3];
-        nl[0] = mul_i<1>(csub(cscale(e[2], kyd), cscale(e[1], kz)));
-        nl[1] = mul_i<1>(csub(cscale(e[0], kz), cscale(e[2], kxd)));
-        nl[2] = mul_i<1>(csub(cscale(e[1], kxd), cscale(e[0], kyd)));
-        const double inv = step == 0 ? 1.0 / (1.0 + aa) : 1.0 / (1.5 + aa);
+        cplx dn[3];
+        dt_curl(e, dt * kx, dt * ky, dkz, dn);
+        const double inv = step == 0 ? inv1[m] : inv2[m];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const cplx b = bs[c * nbox + own[m]];
-          if (step == 0) {
-            bn[m][c] = cscale(cadd(b, cscale(nl[c], dt)), inv);
-          } else {
-            bn[m][c] = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), h[m][c]), inv);
-          }
-          h[m][c] = csub(cscale(b, -0.5), cscale(nl[c], dt));
-        }
+        for (int c = 0; c < 3; ++c) bn[m][c] = sbdf_update(bs[c * nbox + own[m]], dn[c], h[m][c], inv, step);
       }
       __syncthreads();
 #pragma unroll
@@ -754,7 +774,7 @@ __device__ __forceinline__ void sweep_conv_global(const SweepArgs& a, const Prob
   const int M = a.M, K = (a.M - 1) / 2;
   const size_t fbox = (size_t)3 * M * M;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double kz = pb.kz, dt = pb.dt;
+  const double kz = pb.kz, dt = pb.dt, dkz = dt * kz;
   cplx* buf[2] = {a.Bc, a.T1c};
   cplx* Hg = a.Hc;
   for (int n = a.n0; n < a.P; ++n) {
@@ -788,7 +808,7 @@ __device__ __forceinline__ void sweep_conv_global(const SweepArgs& a, const Prob
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx aby = cmul(fm.ap, by);
           e[0] = cadd(e[0], mul_i<1>(aby));
-          e[1] = csub(e[1], cadd(mul_i<1>(cmul(fm.ap, bx)), cmul(fm.ap, bz)));
+          e[1] = csub(e[1], cmul(fm.ap, cadd(mul_i<1>(bx), bz)));
           e[2] = cadd(e[2], aby);
         }
         if (ky + 1 <= Kc) {
@@ -796,14 +816,14 @@ __device__ __forceinline__ void sweep_conv_global(const SweepArgs& a, const Prob
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx aby = cmul(fm.am, by);
           e[0] = csub(e[0], mul_i<1>(aby));
-          e[1] = cadd(e[1], csub(mul_i<1>(cmul(fm.am, bx)), cmul(fm.am, bz)));
+          e[1] = cadd(e[1], cmul(fm.am, csub(mul_i<1>(bx), bz)));
           e[2] = cadd(e[2], aby);
         }
         if (kx - 1 >= -Kc) {
           const int si = (ky + Kc) * Mc + kx - 1 + Kc;
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx bbx = cmul(fm.bp, bx);
-          e[0] = csub(e[0], cadd(mul_i<1>(cmul(fm.bp, bz)), cmul(fm.bp, by)));
+          e[0] = csub(e[0], cmul(fm.bp, cadd(mul_i<1>(bz), by)));
           e[1] = cadd(e[1], bbx);
           e[2] = cadd(e[2], mul_i<1>(bbx));
         }
@@ -811,28 +831,20 @@ __device__ __forceinline__ void sweep_conv_global(const SweepArgs& a, const Prob
           const int si = (ky + Kc) * Mc + kx + 1 + Kc;
           const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
           const cplx bbx = cmul(fm.bm, bx);
-          e[0] = cadd(e[0], csub(mul_i<1>(cmul(fm.bm, bz)), cmul(fm.bm, by)));
+          e[0] = cadd(e[0], cmul(fm.bm, csub(mul_i<1>(bz), by)));
           e[1] = cadd(e[1], bbx);
           e[2] = csub(e[2], mul_i<1>(bbx));
         }
         const double kxd = kx, kyd = ky;
         const double aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / pb.Rm;
-        cplx nl[3];
-        nl[0] = mul_i<1>(csub(cscale(e[2], kyd), cscale(e[1], kz)));
-        nl[1] = mul_i<1>(csub(cscale(e[0], kz), cscale(e[2], kxd)));
-        nl[2] = mul_i<1>(csub(cscale(e[1], kxd), cscale(e[0], kyd)));
+        cplx dn[3];
+        dt_curl(e, dt * kx, dt * ky, dkz, dn);
         const double inv = step == 0 ? 1.0 / (1.0 + aa) : 1.0 / (1.5 + aa);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const cplx b = bs[c * nbox + i];
-          cplx bn;
-          if (step == 0) {
-            bn = cscale(cadd(b, cscale(nl[c], dt)), inv);
-          } else {
-            bn = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), Hg[c * nbox + i]), inv);
-          }
-          Hg[c * nbox + i] = csub(cscale(b, -0.5), cscale(nl[c], dt));
-          bo[c * nbox + i] = bn;
+          cplx hc = step == 0 ? czero() : Hg[c * nbox + i];
+          bo[c * nbox + i] = sbdf_update(bs[c * nbox + i], dn[c], hc, inv, step);
+          Hg[c * nbox + i] = hc;
         }
       }
       __syncthreads();
