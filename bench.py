@@ -681,8 +681,10 @@ def main():
     cols_b, rows_b = kernel_bytes(N, P)
     dominant = ("cols", ms_cols, cols_b) if ms_cols >= ms_rows else ("rows", ms_rows, rows_b)
     achieved = dominant[2] / (dominant[1] * 1e-3) / 1e9
+    re_, rw = pd.variants(N, 0)[tuned[0]]
+    rows_name = "k_rows<128,%d,%d,0,%s>" % (re_, abs(rw), "true" if rw < 0 else "false")
     dom_name = ("k_cols<128,%d,%d>" % tuple(pd.variants(N, 1)[tuned[1]]) if dominant[0] == "cols"
-                else "k_rows<128,%d,%d>" % tuple(pd.variants(N, 0)[tuned[0]]))
+                else rows_name)
     fine_rate = N * N * P / (ms_fstep * 1e-3)
     alg_per_mode = (cols_b + rows_b) / (N * N * P)
 
@@ -728,7 +730,7 @@ def main():
         },
         "autotune": {"rows_variant": list(pd.variants(N, 0)[tuned[0]]),
                      "cols_variant": list(pd.variants(N, 1)[tuned[1]]),
-                     "note": "rows: (values a lane, waves a workgroup); cols: (values a lane, columns a workgroup)"},
+                     "note": "rows: (values a lane, waves a workgroup; negative: state and history loaded with the row); cols: (values a lane, columns a workgroup)"},
         "fine_sweep": {
             "mode_steps_per_s": fine_rate,
             "ms_per_fine_step_all_slices": ms_fstep,

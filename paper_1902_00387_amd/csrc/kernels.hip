@@ -112,7 +112,7 @@ __device__ __forceinline__ cplx rk_update(cplx nl, double L, double d, double dt
 // mode 0: start of a slice (inverse transform of the state only);
 // mode 1: SBDF1 update; mode 2: SBDF2 update; RKS = j > 0 (mode ROW_RK + j):
 // end of Runge-Kutta stage j (stage sums in R).  last: skip the inverse.
-template <int N, int E, int RKS = 0>
+template <int N, int E, int RKS = 0, bool PF = false>
 __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cplx* __restrict__ B,
                                           cplx* __restrict__ H, const cplx* __restrict__ T2,
                                           cplx* __restrict__ T1, const cplx* __restrict__ tw,
@@ -133,11 +133,28 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
         w[c][e] = (active && kx >= -K && kx <= K) ? B[(c * M + r) * M + kx + K] : czero();
       }
   } else {
-    // all three components' loads are issued before the first transform
+    // all three components' loads are issued before the first transform;
+    // with PF (SBDF) also the state and history of the lane's box modes, so
+    // the row waits for global memory once (more registers: fewer waves)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int e = 0; e < E; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : czero();
+    constexpr bool PRE = PF && RKS == 0;
+    cplx bo[3][PRE ? E : 1], ho[3][PRE ? E : 1];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int kx = signed_k(j + T * e, N);
+        const bool in = active && kx >= -K && kx <= K;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int idx = (c * M + r) * M + kx + K;
+          bo[c][e] = in ? B[idx] : czero();
+          ho[c][e] = (in && mode != 1) ? H[idx] : czero();
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, twr);
     const double sc = 1.0 / ((double)N * (double)N);
@@ -167,14 +184,14 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const int idx = (c * M + r) * M + kx + K;
-            const cplx b = B[idx];
+            const cplx b = PRE ? bo[c][PRE ? e : 0] : B[idx];
             cplx bn;
             if (mode == 1) {
               const double inv = 1.0 / (1.0 + a);
               bn = cscale(cadd(b, cscale(nl[c], dt)), inv);
             } else {
               const double inv = 1.0 / (1.5 + a);
-              const cplx h = H[idx];
+              const cplx h = PRE ? ho[c][PRE ? e : 0] : H[idx];
               bn = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), h), inv);
             }
             H[idx] = csub(cscale(b, -0.5), cscale(nl[c], dt));
@@ -327,7 +344,7 @@ __host__ __device__ constexpr int tile_elems(int lanes) {
 
 // ---------------------------------------------------------------------------
 // Multi-launch path: one launch per phase over every (field, tile).
-template <int N, int E, int W, int RKS>
+template <int N, int E, int W, int RKS, bool PF = false>
 __global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int mode, int last) {
   using G = Geo<N, E>;
   constexpr int RPW = W * 64 / G::T;
@@ -340,7 +357,7 @@ __global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int 
   Problem p = pb;
   if (fb.fRm != nullptr) p.Rm = fb.fRm[f];
   if (fb.fkz != nullptr) p.kz = fb.fkz[f];
-  row_phase<N, E, RKS>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
+  row_phase<N, E, RKS, PF>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
                        fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, p, mode, last != 0,
                        RKS > 0 ? fb.R + 4 * f * box : nullptr);
 }
@@ -997,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_norm2(const cplx* __restrict__ x, size_
 
 // ---------------------------------------------------------------------------
 // Host launchers.
-template <int N, int E, int W>
+template <int N, int E, int W, bool PF = false>
 static hipError_t launch_rows_v(const FieldBatch& fb, const Problem& pb, int nfields, int mode,
                                 int last, hipStream_t st) {
   using G = Geo<N, E>;
@@ -1010,7 +1027,7 @@ static hipError_t launch_rows_v(const FieldBatch& fb, const Problem& pb, int nfi
     case 2: hipLaunchKernelGGL((k_rows<N, E, W, 2>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
     case 3: hipLaunchKernelGGL((k_rows<N, E, W, 3>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
     case 4: hipLaunchKernelGGL((k_rows<N, E, W, 4>), grid, dim3(64 * W), 0, st, fb, pb, mode, last); break;
-    default: hipLaunchKernelGGL((k_rows<N, E, W, 0>), grid, dim3(64 * W), 0, st, fb, pb, mode, last);
+    default: hipLaunchKernelGGL((k_rows<N, E, W, 0, PF>), grid, dim3(64 * W), 0, st, fb, pb, mode, last);
   }
   return hipGetLastError();
 }
@@ -1036,8 +1053,10 @@ struct ColsVariant {
   ColsFn fn;
 };
 
-// Candidates: rows -- values a lane E (8 or 4), waves a workgroup W;
-// columns -- values a lane E, columns a workgroup TX (lanes <= 1024, LDS <= 160 KB).
+// Candidates: rows -- values a lane E (8 or 4), waves a workgroup W, W < 0 for
+// the form that loads the state and history with the row (faster on small
+// batches, fewer waves); columns -- values a lane E, columns a workgroup TX
+// (lanes <= 1024, LDS <= 160 KB).
 template <int N>
 struct Variants;
 template <>
@@ -1055,7 +1074,8 @@ struct Variants<64> {
   static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<64, 8, 1>},
                                          {8, 2, launch_rows_v<64, 8, 2>},
                                          {4, 1, launch_rows_v<64, 4, 1>},
-                                         {4, 2, launch_rows_v<64, 4, 2>}};
+                                         {4, 2, launch_rows_v<64, 4, 2>},
+                                         {4, -1, launch_rows_v<64, 4, 1, true>}};
   static constexpr ColsVariant cols[] = {{4, 32, launch_cols_v<64, 4, 32, 4>},
                                          {4, 16, launch_cols_v<64, 4, 16, 4>},
                                          {8, 32, launch_cols_v<64, 8, 32, 2>},
@@ -1066,7 +1086,9 @@ struct Variants<128> {
   static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<128, 8, 1>},
                                          {8, 2, launch_rows_v<128, 8, 2>},
                                          {4, 1, launch_rows_v<128, 4, 1>},
-                                         {4, 2, launch_rows_v<128, 4, 2>}};
+                                         {4, 2, launch_rows_v<128, 4, 2>},
+                                         {4, -1, launch_rows_v<128, 4, 1, true>},
+                                         {4, -2, launch_rows_v<128, 4, 2, true>}};
   static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<128, 4, 16, 4>},
                                          {4, 8, launch_cols_v<128, 4, 8, 4>},
                                          {8, 16, launch_cols_v<128, 8, 16, 2>},
@@ -1077,7 +1099,8 @@ template <>
 struct Variants<256> {
   static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<256, 8, 1>},
                                          {8, 2, launch_rows_v<256, 8, 2>},
-                                         {4, 1, launch_rows_v<256, 4, 1>}};
+                                         {4, 1, launch_rows_v<256, 4, 1>},
+                                         {4, -1, launch_rows_v<256, 4, 1, true>}};
   static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<256, 4, 16, 4>},
                                          {4, 8, launch_cols_v<256, 4, 8, 4>},
                                          {8, 16, launch_cols_v<256, 8, 16, 2>},
@@ -1106,16 +1129,22 @@ static int size_slot(int N) {
 static int g_rows_choice[6] = {0, 0, 0, 0, 0, 0};
 static int g_cols_choice[6] = {0, 0, 0, 0, 0, 0};
 
+// a batch's own choice (FieldBatch::rows_v / cols_v, if valid) before the
+// process-wide one
 template <int N>
 static hipError_t launch_rows(const FieldBatch& fb, const Problem& pb, int nfields, int mode,
                               int last, hipStream_t st) {
-  return Variants<N>::rows[g_rows_choice[size_slot(N)]].fn(fb, pb, nfields, mode, last, st);
+  constexpr int nv = (int)(sizeof(Variants<N>::rows) / sizeof(RowsVariant));
+  const int v = fb.rows_v >= 0 && fb.rows_v < nv ? fb.rows_v : g_rows_choice[size_slot(N)];
+  return Variants<N>::rows[v].fn(fb, pb, nfields, mode, last, st);
 }
 
 template <int N>
 static hipError_t launch_cols(const FieldBatch& fb, const Problem& pb, int nfields, int step,
                               hipStream_t st, int stage = 0) {
-  return Variants<N>::cols[g_cols_choice[size_slot(N)]].fn(fb, pb, nfields, step, stage, st);
+  constexpr int nv = (int)(sizeof(Variants<N>::cols) / sizeof(ColsVariant));
+  const int v = fb.cols_v >= 0 && fb.cols_v < nv ? fb.cols_v : g_cols_choice[size_slot(N)];
+  return Variants<N>::cols[v].fn(fb, pb, nfields, step, stage, st);
 }
 
 template <int N>

@@ -46,6 +46,7 @@ struct FieldBatch {
   const double* fkz = nullptr;  // [f] per-field kz
   const int* map = nullptr;     // [launch row] field index; rows >= *count exit at once
   const int* count = nullptr;   // device count of active launch rows
+  int rows_v = -1, cols_v = -1;  // launch-shape variants for this batch (-1: process-wide choice)
 };
 
 struct SweepArgs;

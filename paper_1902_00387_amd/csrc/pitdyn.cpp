@@ -296,6 +296,7 @@ pd_status pd_set_pipeline(pd_ctx* c, int chunks, int speculate) {
   if (!c) return PD_EINVAL;
   if (chunks < 0 || chunks > 64) return fail(c, PD_EINVAL, "chunks must be in [0, 64]");
   if (speculate < 0 || speculate > 2) return fail(c, PD_EINVAL, "speculate must be 0, 1 or 2");
+  if (chunks != c->pipe_chunks) c->chunk_rv = c->chunk_cv = -1;  // tuned for other runs
   c->pipe_chunks = chunks;
   c->pipe_spec = speculate;
   return PD_OK;
@@ -358,6 +359,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   PD_HIP(c, c->tw.ensure(sizeof(cplx) * N), "alloc twiddles");
   PD_HIP(c, hipMemcpy(c->tw.p, tw.data(), sizeof(cplx) * N, hipMemcpyHostToDevice), "copy");
   c->have_problem = true;
+  c->chunk_rv = c->chunk_cv = -1;  // tuned for another grid or slice count
   return PD_OK;
 }
 
@@ -420,6 +422,7 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
     PD_HIP(c, hipMemcpy(c->ftab.p, ft.data(), ft.size() * sizeof(double), hipMemcpyHostToDevice), "copy");
   }
   c->have_time = true;
+  c->chunk_rv = c->chunk_cv = -1;
   return ensure_rk_buffers(c);
 }
 
@@ -766,10 +769,18 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (reps < 1) return fail(c, PD_EINVAL, "reps must be >= 1");
   DeviceGuard dg(c->device);
-  const std::string key = tune_key(c->device, c->N, c->P);
-  int rv = 0, cv = 0;
+  const int P = c->P;
+  // slices of one run of the pipelined schedule (0: not pipelined)
+  const int runs = std::min(c->pipe_chunks, P);
+  const int Pc = runs >= 2 ? (P + runs - 1) / runs : 0;
+  const std::string key = tune_key(c->device, c->N, P);
+  const std::string key_c = tune_key(c->device, c->N, Pc);
+  int rv = 0, cv = 0, rvc = -1, cvc = -1;
   if (cache_path && cache_lookup(cache_path, key, &rv, &cv) &&
+      (Pc == 0 || Pc >= P || cache_lookup(cache_path, key_c, &rvc, &cvc)) &&
       pd::variant_select(c->N, rv, cv) == 0) {
+    c->chunk_rv = Pc > 0 && Pc < P ? rvc : -1;
+    c->chunk_cv = Pc > 0 && Pc < P ? cvc : -1;
     if (chosen) {
       chosen[0] = rv;
       chosen[1] = cv;
@@ -779,7 +790,6 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   }
   hipStream_t st = c->stream;
   const size_t box = c->box_elems();
-  const int P = c->P;
   hipEvent_t ev[2];
   for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
   struct EvFree {
@@ -796,33 +806,68 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   const pd::Problem pf = make_problem(c, c->dtf);
   int cur_r = 0, cur_c = 0;
   pd::variant_current(c->N, &cur_r, &cur_c);
-  auto timed = [&](int kind, float* out) -> hipError_t {
+  // launches of the row (kind 0, an SBDF2 step) or column phase over nf
+  // fields with batch variants (rows_v, cols_v)
+  auto timed = [&](int kind, int nf, int rows_v, int cols_v, float* out) -> hipError_t {
+    pd::FieldBatch f = fb;
+    f.rows_v = rows_v;
+    f.cols_v = cols_v;
     hipError_t e = hipEventRecord(ev[0], st);
     for (int i = 0; i < reps && e == hipSuccess; ++i)
-      e = kind == 0 ? pd::rows(c->N, fb, pf, P, 2, 0, st) : pd::cols(c->N, fb, pf, P, 1, st);
+      e = kind == 0 ? pd::rows(c->N, f, pf, nf, 2, 0, st) : pd::cols(c->N, f, pf, nf, 1, st);
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
     if (e == hipSuccess) e = hipEventElapsedTime(out, ev[0], ev[1]);
     return e;
   };
-  PD_HIP(c, hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx), hipMemcpyDeviceToDevice, st), "copy");
-  PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
-  float best[2] = {1e30f, 1e30f};
-  int bestv[2] = {cur_r, cur_c};
-  for (int kind = 0; kind < 2; ++kind) {
-    const int nv = pd::variant_count(c->N, kind);
-    for (int v = 0; v < nv; ++v) {
-      pd::variant_select(c->N, kind == 0 ? v : bestv[0], kind == 1 ? v : cur_c);
-      float t = 0;
-      PD_HIP(c, timed(kind, &t), "autotune");  // warm-up
-      PD_HIP(c, timed(kind, &t), "autotune");
-      if (t < best[kind]) {
-        best[kind] = t;
-        bestv[kind] = v;
+  // values a lane of a variant
+  auto vals = [&](int kind, int v) {
+    int e = 0, w = 0;
+    pd::variant_describe(c->N, kind, v, &e, &w);
+    return e;
+  };
+  // fastest row variant, then the fastest column variant, on nf fields;
+  // with same_e, only variants with the values a lane of (e_r, e_c)
+  auto tune = [&](int nf, int bestv[2], float best[2], bool same_e, int e_r,
+                  int e_c) -> hipError_t {
+    best[0] = best[1] = 1e30f;
+    bestv[0] = same_e ? e_r : cur_r;
+    bestv[1] = same_e ? e_c : cur_c;
+    for (int kind = 0; kind < 2; ++kind) {
+      const int nv = pd::variant_count(c->N, kind);
+      for (int v = 0; v < nv; ++v) {
+        if (same_e && vals(kind, v) != vals(kind, kind == 0 ? e_r : e_c)) continue;
+        const int r = kind == 0 ? v : bestv[0], cc = kind == 1 ? v : cur_c;
+        float t = 0;
+        hipError_t e = timed(kind, nf, r, cc, &t);  // warm-up
+        if (e == hipSuccess) e = timed(kind, nf, r, cc, &t);
+        if (e != hipSuccess) return e;
+        if (t < best[kind]) {
+          best[kind] = t;
+          bestv[kind] = v;
+        }
       }
     }
-  }
+    return hipSuccess;
+  };
+  PD_HIP(c, hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx), hipMemcpyDeviceToDevice, st), "copy");
+  PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
+  float best[2];
+  int bestv[2];
+  PD_HIP(c, tune(P, bestv, best, false, 0, 0), "autotune");
   pd::variant_select(c->N, bestv[0], bestv[1]);
+  c->chunk_rv = c->chunk_cv = -1;
+  if (Pc > 0 && Pc < P) {
+    // the pipelined schedule's runs of Pc slices: their own choice among the
+    // variants with the values a lane of the full-batch choice, so that both
+    // orders stay bitwise equal
+    float bc[2];
+    int vc[2];
+    PD_HIP(c, tune(Pc, vc, bc, true, bestv[0], bestv[1]), "autotune");
+    c->chunk_rv = vc[0];
+    c->chunk_cv = vc[1];
+    if (cache_path) cache_store(cache_path, key_c, vc[0], vc[1]);
+  }
   if (chosen) {
     chosen[0] = bestv[0];
     chosen[1] = bestv[1];

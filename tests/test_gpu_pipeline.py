@@ -10,10 +10,12 @@ pytestmark = pytest.mark.gpu
 
 
 def run(lib, chunks, P=10, N=32, tol=1e-10, max_iter=None, flow="gp", Nc=16, resume=None, form=0,
-        spec=2):
+        spec=2, scheme=None):
     with lib.Context(0) as ctx:
         ctx.set_problem(flow, 60.0, 0.57, N)
         ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, Nc)
+        if scheme is not None:
+            ctx.set_scheme(*scheme)
         ctx.set_coarse_form(form)
         ctx.set_pipeline(chunks, spec)
         b0 = initial_field(N, 0.57, 77)
@@ -57,4 +59,45 @@ def test_pipelined_resume_and_fft_coarse_form(lib):
     r0, U0, _ = run(lib, 0, P=6, tol=1e-8, form=1)
     r1, U1, _ = run(lib, 4, P=6, tol=1e-8, form=1)
     assert r0["k_con"] == r1["k_con"] > 0
+    assert np.array_equal(U0, U1)
+
+
+@pytest.mark.parametrize("scheme,form", [(("rk443", "rk443"), 3), (("sbdf2", "rk222"), 1),
+                                         (("rk443", "sbdf2"), 0)])
+def test_pipelined_runge_kutta_and_coarse_forms_bitwise(lib, scheme, form):
+    """Runge-Kutta fine or coarse steppers with the multi-launch (3), FFT (1)
+    and automatic (0) coarse forms: pipelined = plain order, bitwise."""
+    r0, U0, G0 = run(lib, 0, P=8, tol=1e-9, scheme=scheme, form=form)
+    r1, U1, G1 = run(lib, 3, P=8, tol=1e-9, scheme=scheme, form=form)
+    assert r0["k_con"] == r1["k_con"] > 0 and r0["iters"] == r1["iters"]
+    assert r0["sigma"][:r0["iters"]] == r1["sigma"][:r1["iters"]]
+    assert np.array_equal(U0, U1)
+    assert np.array_equal(G0, G1)
+
+
+def test_pipelined_with_autotuned_run_variants_is_bitwise(lib):
+    """The autotuner's launch shapes for the runs of slices (same values a
+    lane as the full batch's) keep the pipelined order bitwise equal to the
+    plain order; the plain order is run after the pipelined one because a new
+    chunk count drops the runs' choice."""
+    N, P = 64, 8
+    b0 = initial_field(N, 0.57, 12)
+    with lib.Context(0) as ctx:
+        ctx.set_problem("gp", 60.0, 0.57, N)
+        ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, 32)
+        ctx.set_initial(b0)
+        ctx.parareal(0.0, 0)
+        try:
+            ctx.autotune(3)
+            ctx.set_initial(b0)
+            r1 = ctx.parareal(1e-9, P + 1)
+            U1 = ctx.get_slices()
+            ctx.set_pipeline(0)
+            ctx.set_initial(b0)
+            r0 = ctx.parareal(1e-9, P + 1)
+            U0 = ctx.get_slices()
+        finally:
+            lib.select_variant(N, 0, 0)
+    assert r0["k_con"] == r1["k_con"] > 0
+    assert r0["sigma"][:r0["iters"]] == r1["sigma"][:r1["iters"]]
     assert np.array_equal(U0, U1)
