@@ -237,12 +237,7 @@ pd_status pd_profile_fine(pd_ctx* ctx, int reps, double* ms);
    (either may be NULL).  With cache_path non-NULL the choice is first looked
    up in that JSON file (key "<gfx arch>|<N>|<n_slices>"; ms = 0 on a hit) and
    stored there after timing.  Variants give identical results bitwise only
-   with equal values a lane; all agree with the oracle to the parity bar.
-   With the pipelined schedule on (pd_set_pipeline, chunks >= 2) it also
-   picks, among the variants with the chosen values a lane, the fastest for
-   a run of ceil(n_slices / chunks) slices and keeps them in the context for
-   the runs' fine sweeps (cache key with that slice count); pd_set_pipeline
-   with another chunk count, pd_set_problem and pd_set_time drop them. */
+   with equal values a lane; all agree with the oracle to the parity bar. */
 pd_status pd_autotune(pd_ctx* ctx, int reps, const char* cache_path, int* chosen, double* ms);
 /* Variant table: v = -1 puts the number of variants of `kind` (0 rows,
    1 columns) for grid N in *a; v >= 0 describes variant v (rows: *a values a

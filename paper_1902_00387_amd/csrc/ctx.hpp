@@ -22,7 +22,6 @@ struct pd_ctx {
   hipStream_t fst = nullptr;       // pipelined Parareal: fine streams
   int pipe_spec = 2;               // pipelined: which chunks of the next fine sweep start early
   int pipe_chunks = 2;             // slice chunks of the pipelined Parareal (< 2: off)
-  int chunk_rv = -1, chunk_cv = -1;  // launch variants of a chunk's fine sweep (-1: process-wide)
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;

@@ -296,7 +296,6 @@ pd_status pd_set_pipeline(pd_ctx* c, int chunks, int speculate) {
   if (!c) return PD_EINVAL;
   if (chunks < 0 || chunks > 64) return fail(c, PD_EINVAL, "chunks must be in [0, 64]");
   if (speculate < 0 || speculate > 2) return fail(c, PD_EINVAL, "speculate must be 0, 1 or 2");
-  if (chunks != c->pipe_chunks) c->chunk_rv = c->chunk_cv = -1;  // tuned for other runs
   c->pipe_chunks = chunks;
   c->pipe_spec = speculate;
   return PD_OK;
@@ -359,7 +358,6 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   PD_HIP(c, c->tw.ensure(sizeof(cplx) * N), "alloc twiddles");
   PD_HIP(c, hipMemcpy(c->tw.p, tw.data(), sizeof(cplx) * N, hipMemcpyHostToDevice), "copy");
   c->have_problem = true;
-  c->chunk_rv = c->chunk_cv = -1;  // tuned for another grid or slice count
   return PD_OK;
 }
 
@@ -422,7 +420,6 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
     PD_HIP(c, hipMemcpy(c->ftab.p, ft.data(), ft.size() * sizeof(double), hipMemcpyHostToDevice), "copy");
   }
   c->have_time = true;
-  c->chunk_rv = c->chunk_cv = -1;
   return ensure_rk_buffers(c);
 }
 
@@ -770,17 +767,10 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   if (reps < 1) return fail(c, PD_EINVAL, "reps must be >= 1");
   DeviceGuard dg(c->device);
   const int P = c->P;
-  // slices of one run of the pipelined schedule (0: not pipelined)
-  const int runs = std::min(c->pipe_chunks, P);
-  const int Pc = runs >= 2 ? (P + runs - 1) / runs : 0;
   const std::string key = tune_key(c->device, c->N, P);
-  const std::string key_c = tune_key(c->device, c->N, Pc);
-  int rv = 0, cv = 0, rvc = -1, cvc = -1;
+  int rv = 0, cv = 0;
   if (cache_path && cache_lookup(cache_path, key, &rv, &cv) &&
-      (Pc == 0 || Pc >= P || cache_lookup(cache_path, key_c, &rvc, &cvc)) &&
       pd::variant_select(c->N, rv, cv) == 0) {
-    c->chunk_rv = Pc > 0 && Pc < P ? rvc : -1;
-    c->chunk_cv = Pc > 0 && Pc < P ? cvc : -1;
     if (chosen) {
       chosen[0] = rv;
       chosen[1] = cv;
@@ -820,23 +810,14 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
     if (e == hipSuccess) e = hipEventElapsedTime(out, ev[0], ev[1]);
     return e;
   };
-  // values a lane of a variant
-  auto vals = [&](int kind, int v) {
-    int e = 0, w = 0;
-    pd::variant_describe(c->N, kind, v, &e, &w);
-    return e;
-  };
-  // fastest row variant, then the fastest column variant, on nf fields;
-  // with same_e, only variants with the values a lane of (e_r, e_c)
-  auto tune = [&](int nf, int bestv[2], float best[2], bool same_e, int e_r,
-                  int e_c) -> hipError_t {
+  // fastest row variant, then the fastest column variant, on nf fields
+  auto tune = [&](int nf, int bestv[2], float best[2]) -> hipError_t {
     best[0] = best[1] = 1e30f;
-    bestv[0] = same_e ? e_r : cur_r;
-    bestv[1] = same_e ? e_c : cur_c;
+    bestv[0] = cur_r;
+    bestv[1] = cur_c;
     for (int kind = 0; kind < 2; ++kind) {
       const int nv = pd::variant_count(c->N, kind);
       for (int v = 0; v < nv; ++v) {
-        if (same_e && vals(kind, v) != vals(kind, kind == 0 ? e_r : e_c)) continue;
         const int r = kind == 0 ? v : bestv[0], cc = kind == 1 ? v : cur_c;
         float t = 0;
         hipError_t e = timed(kind, nf, r, cc, &t);  // warm-up
@@ -854,20 +835,8 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
   float best[2];
   int bestv[2];
-  PD_HIP(c, tune(P, bestv, best, false, 0, 0), "autotune");
+  PD_HIP(c, tune(P, bestv, best), "autotune");
   pd::variant_select(c->N, bestv[0], bestv[1]);
-  c->chunk_rv = c->chunk_cv = -1;
-  if (Pc > 0 && Pc < P) {
-    // the pipelined schedule's runs of Pc slices: their own choice among the
-    // variants with the values a lane of the full-batch choice, so that both
-    // orders stay bitwise equal
-    float bc[2];
-    int vc[2];
-    PD_HIP(c, tune(Pc, vc, bc, true, bestv[0], bestv[1]), "autotune");
-    c->chunk_rv = vc[0];
-    c->chunk_cv = vc[1];
-    if (cache_path) cache_store(cache_path, key_c, vc[0], vc[1]);
-  }
   if (chosen) {
     chosen[0] = bestv[0];
     chosen[1] = bestv[1];

@@ -75,11 +75,10 @@ def test_pipelined_runge_kutta_and_coarse_forms_bitwise(lib, scheme, form):
     assert np.array_equal(G0, G1)
 
 
-def test_pipelined_with_autotuned_run_variants_is_bitwise(lib):
-    """The autotuner's launch shapes for the runs of slices (same values a
-    lane as the full batch's) keep the pipelined order bitwise equal to the
-    plain order; the plain order is run after the pipelined one because a new
-    chunk count drops the runs' choice."""
+def test_pipelined_with_autotuned_launch_shapes_is_bitwise(lib):
+    """After the autotuner has picked the launch shapes (among them the row
+    variant that loads state and history with the row), the pipelined order
+    stays bitwise equal to the plain order."""
     N, P = 64, 8
     b0 = initial_field(N, 0.57, 12)
     with lib.Context(0) as ctx:
