@@ -191,6 +191,43 @@ def test_config2_sampled_fine_sweep(ctx):
         assert rel(y[n], F(x[n], float(n))) <= TOL, n
 
 
+def test_config2_parareal_full_size(ctx):
+    """The Galloway-Proctor 128^2 workload at its full size (Rm = 100, kz =
+    0.57, T = 64 over 64 slices, fine dt = 2e-3, coarse dt = 1e-2 on 64^2,
+    tol 1e-8, pipelined as the benchmark runs it): properties that hold at
+    any size.  The converged iterate agrees with the serial fine solve (the
+    library's own F, slice after slice) and, on sampled slices, the oracle's
+    F maps U_n to U_{n+1}, both to 1e-7 (Parareal stops once the relative
+    change of U_P between iterations is <= 1e-8); the growth rate equals the
+    serial solve's to 1e-6, and the defects fall monotonically."""
+    N, kz, Rm, T, P, dtf = 128, 0.57, 100.0, 64.0, 64, 2e-3
+    b0 = initial_field(N, kz, 1)
+    ctx.set_problem("gp", Rm, kz, N)
+    ctx.set_time(T, P, dtf, 1e-2, 64)
+    ctx.set_initial(b0)
+    print("full-size parareal", flush=True)
+    rep = ctx.parareal(1e-8, P)
+    assert 0 < rep["k_con"] <= P
+    sig = rep["sigma"][:rep["iters"]]
+    assert sig[-1] <= 1e-8 and all(b < a for a, b in zip(sig, sig[1:]))
+    U = ctx.get_slices()
+    gam = ctx.growth_rate()
+    # serial fine solve on the GPU, slice after slice
+    u = dev(b0[None])
+    serial = [b0]
+    for n in range(P):
+        u = ctx.fine([float(n)], u)
+        serial.append(u[0].cpu().numpy())
+    d_serial = max(rel(U[n], serial[n]) for n in (1, 17, 40, 64))
+    gs = opr.growth_rate([opr.norm2(x) for x in serial], np.arange(P + 1.0))
+    F = stepper.SliceSolver("gp", Rm, kz, N, 1.0, dtf)
+    d_oracle = max(rel(U[n + 1], F(U[n], float(n))) for n in (0, 51))
+    print(f"k_con {rep['k_con']}: vs serial {d_serial:.1e}, vs oracle F {d_oracle:.1e}, "
+          f"growth {abs(gam - gs):.1e}", flush=True)
+    assert d_serial <= 1e-7 and d_oracle <= 1e-7
+    assert abs(gam - gs) <= 1e-6
+
+
 def test_invalid_arguments(ctx, lib):
     torch = _torch()
     with pytest.raises(lib.PitdynError) as e:
