@@ -38,3 +38,20 @@ def test_null_context_calls_fail_cleanly():
     assert pd.lib.pd_set_path(None, 0) == pd.EINVAL
     assert pd.lib.pd_last_error(None) == b"null context"
     assert pd.lib.pd_create(None, 0) == pd.EINVAL
+
+
+def test_report_struct_matches_header():
+    """The binding's pd_report mirror has the header's fields, in order, with
+    the same types and array length."""
+    import paper_1902_00387_amd as pd
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} pd_report;", text, flags=re.S).group(1)
+    fields = re.findall(r"(int|double)\s+([A-Za-z_0-9]+)(\[PD_MAX_ITER\])?;", body)
+    mirror = pd.Report._fields_
+    assert [n for _, n, _ in fields] == [n for n, _ in mirror]
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double}
+    for (t, n, arr), (_, ct) in zip(fields, mirror):
+        want = ctype[t] * pd.MAX_ITER if arr else ctype[t]
+        assert ctypes.sizeof(ct) == ctypes.sizeof(want), n
+    assert "#define PD_MAX_ITER %d" % pd.MAX_ITER in open(HEADER).read()
