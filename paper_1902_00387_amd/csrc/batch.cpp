@@ -167,7 +167,7 @@ pd_status build(pd_batch* b) {
   b->jobsG.clear();
   for (auto& in : b->inst) {
     const int Mc = box_M(in.Nc);
-    in.lds_job = Mc <= 45;
+    in.lds_job = pd::conv_lds_width(Mc);
     in.ftab_off = ftab_total;
     if (in.flow == PD_FLOW_GP) ftab_total += (size_t)4 * in.P * in.nc;
     if (!in.lds_job) cws_total += (size_t)9 * Mc * Mc;

@@ -567,7 +567,7 @@ __device__ __forceinline__ FlowModes flow_modes(const Problem& pb, double t) {
 }
 
 constexpr int CONV_LANES = 1024;
-constexpr int CONV_MMAX = 45;  // coarse box width held in LDS (N_C <= 64)
+constexpr int CONV_MMAX = 43;  // widest coarse box held in LDS (N_C = 64)
 constexpr int CONV_MPL = (CONV_MMAX * CONV_MMAX + CONV_LANES - 1) / CONV_LANES;  // modes a lane
 
 // dt N = dt i k x E with (dkx, dky, dkz) = dt k: component c is
@@ -594,17 +594,20 @@ __device__ __forceinline__ cplx sbdf_update(cplx b, cplx d, cplx& h, double inv,
   return bn;
 }
 
-// One workgroup runs the coarse sweep; lane l owns box modes l + CONV_LANES*m
-// (state and history in registers) and reads neighbours from LDS.
-__device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem& pb, int Mc,
+// One workgroup runs the coarse sweep of an MC x MC coarse box (a compile-time
+// width, so the neighbours' offsets and the index arithmetic are constants);
+// lane l owns box modes l + CONV_LANES*m (state and history in registers)
+// and reads neighbours from LDS.
+template <int MC>
+__device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem& pb, int,
                                                cplx* bs, double (*rs)[CONV_LANES]) {
-  const int Kc = (Mc - 1) / 2;
-  const int nbox = Mc * Mc;
+  constexpr int Mc = MC;
+  constexpr int Kc = (Mc - 1) / 2;
+  constexpr int nbox = Mc * Mc;
   const int M = a.M, K = (a.M - 1) / 2;
   const size_t fbox = (size_t)3 * M * M;
   const int tid = threadIdx.x, nt = blockDim.x;
   const double kz = pb.kz, dt = pb.dt, dkz = dt * kz;
-  // owned modes
   // owned modes and their implicit factors (SBDF1, SBDF2)
   int own[CONV_MPL], oky[CONV_MPL], okx[CONV_MPL];
   double inv1[CONV_MPL], inv2[CONV_MPL];
@@ -746,10 +749,11 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
 }
 
 
+template <int MC>
 __global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem pb, int Mc) {
-  __shared__ cplx bs[3 * CONV_MMAX * CONV_MMAX];
+  __shared__ cplx bs[3 * MC * MC];
   __shared__ double rs[2][CONV_LANES];
-  sweep_conv_lds(a, pb, Mc, bs, rs);
+  sweep_conv_lds<MC>(a, pb, Mc, bs, rs);
 }
 
 // Defect sums |U_P - Uprev|^2, |U_P|^2 of one sweep, fixed-order tree.
@@ -903,7 +907,12 @@ __global__ __launch_bounds__(CONV_LANES) void k_sweep_conv_jobs(const SweepJob* 
   }
   if constexpr (LDS_RESIDENT) {
     __shared__ cplx bs[3 * CONV_MMAX * CONV_MMAX];
-    sweep_conv_lds(jb.a, jb.pb, jb.Mc, bs, rs);
+    // the host puts only the widths conv_lds_width accepts here
+    switch (jb.Mc) {
+      case 11: sweep_conv_lds<11>(jb.a, jb.pb, jb.Mc, bs, rs); break;
+      case 21: sweep_conv_lds<21>(jb.a, jb.pb, jb.Mc, bs, rs); break;
+      default: sweep_conv_lds<43>(jb.a, jb.pb, jb.Mc, bs, rs); break;
+    }
   } else {
     sweep_conv_global(jb.a, jb.pb, jb.Mc, rs);
   }
@@ -1354,8 +1363,13 @@ static hipError_t launch_sweep(const SweepArgs& a, const Problem& pb, hipStream_
 
 hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st) {
   const int Mc = 2 * ((Nc - 1) / 3) + 1;
-  if (Mc > CONV_MMAX || pb.scheme != 0) return hipErrorInvalidValue;  // SBDF2 only
-  hipLaunchKernelGGL(k_sweep_conv, dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc);
+  if (!conv_lds_width(Mc) || pb.scheme != 0) return hipErrorInvalidValue;  // SBDF2 only
+  switch (Mc) {
+    case 11: hipLaunchKernelGGL(k_sweep_conv<11>, dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc); break;
+    case 21: hipLaunchKernelGGL(k_sweep_conv<21>, dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc); break;
+    case 43: hipLaunchKernelGGL(k_sweep_conv<43>, dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -104,12 +104,15 @@ int variant_count(int N, int kind);
 int variant_describe(int N, int kind, int v, int* a, int* b);
 int variant_select(int N, int rows_v, int cols_v);
 void variant_current(int N, int* rows_v, int* cols_v);
+// coarse box widths whose convolution-form sweep keeps the box in LDS (a
+// compiled width each): those of N_C = 16, 32, 64
+inline constexpr bool conv_lds_width(int Mc) { return Mc == 11 || Mc == 21 || Mc == 43; }
 // same sweep with the explicit term as the exact spectral convolution with the
 // flow's four Fourier modes (N_C <= 64)
 hipError_t sweep_conv(int Nc, const SweepArgs& a, const Problem& pb, hipStream_t st);
 // many independent coarse sweeps, one workgroup each (convolution form);
-// jobs with Mc <= 45 keep the box in LDS, larger ones in their Bc/T1c/Hc
-// global buffers (3 Mc^2 values each)
+// jobs whose width passes conv_lds_width keep the box in LDS, others in their
+// Bc/T1c/Hc global buffers (3 Mc^2 values each)
 hipError_t sweep_conv_jobs(const SweepJob* d_jobs, int njobs, bool lds_resident, hipStream_t st);
 // full layout [f][3][N][N] <-> compact [f][3][M][M] of the |k| <= (M-1)/2 box
 // (M < box width of N restricts / zero-pads: Fourier re-sampling)
