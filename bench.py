@@ -374,31 +374,48 @@ def _growth(norms, dT):
     return float(np.polyfit(n * dT, np.log(np.asarray(norms)[n]), 1)[0])
 
 
+def nc_sweep_workload(args):
+    """The coarse-grid sweep's workloads.  roberts: the paper's Section 5.2
+    study (its speed-up-vs-N_C figure): Roberts flow, Rm = 512, kz = 2.87,
+    N_F = 128 or 256 (powers of two around the paper's 160), fine ARS(4,4,3)
+    with dt = 1e-2 (5e-3 on 256^2), 10 slices of length 1, tolerance 1e-5 (the
+    paper's accuracy target).  gp128: the headline workload (Galloway-Proctor,
+    Rm = 100, kz = 0.57, 128^2, 64 slices of length 1, fine SBDF2 dt = 2e-3,
+    SBDF2 coarse propagator, tolerance 1e-8)."""
+    if args.nc_sweep_gp:
+        return dict(flow="gp", Rm=RM, kz=KZ, N=N, P=P, T=T, dtf=DT_FINE, scheme="sbdf2",
+                    seed=SEED, tol=TOL, nc_list=(N // 4, N // 2, N),
+                    dtc_cands=(2e-2, 1e-2, 5e-3, 2.5e-3))
+    NF = args.nc_nf
+    return dict(flow="roberts", Rm=512.0, kz=2.87, N=NF, P=10, T=10.0,
+                dtf=1e-2 if NF <= 128 else 5e-3,  # largest stable ARS(4,4,3) step of the grid
+                scheme="rk443", seed=500000, tol=args.nc_tol,
+                nc_list=(NF // 8, NF // 4, NF // 2, NF),
+                dtc_cands=(0.1, 0.05, 0.025, 0.0125, 0.00625, 0.003125))
+
+
 def run_nc_sweep(args):
-    """Coarse-grid sweep (the paper's Section 5.2 study, its speed-up-vs-N_C
-    figure): Roberts flow, Rm = 512, kz = 2.87, N_F = 128 or 256 (powers of two
-    around the paper's 160), fine ARS(4,4,3) with dt = 1e-2 (5e-3 on 256^2),
-    10 slices of length 1,
-    tolerance 1e-5 (the paper's accuracy target).  For every N_C the coarse
-    step is the largest of {0.1, 0.05, ..., 0.003125} whose coarse-only run
-    is still as accurate at T as the smallest step allows (error against the
-    serial fine solution within twice the smallest-step error: accuracy
-    limited by the grid, not by the step).  Reported: k_con, R_f/R_c, time
-    to solution, speed-up over the serial fine solve on the same GPU, and the
-    paper's speed-up model (eq. speed_up) for 10 processors."""
+    """Coarse-grid sweep (nc_sweep_workload).  For every N_C the coarse step
+    is the largest candidate whose coarse-only run is still as accurate at T
+    as the smallest step allows (error against the serial fine solution
+    within twice the smallest-step error: accuracy limited by the grid, not by
+    the step).  Reported: k_con, R_f/R_c, time to solution (the library's default, pipelined, order), speed-up
+    over the serial fine solve on the same GPU, and the paper's speed-up model
+    (eq. speed_up) for as many processors as slices."""
     import numpy as np
     import torch
 
     import paper_1902_00387_amd as pd
     from synthetic import initial_field
-    N, Rm, kz, P, T, tol = args.nc_nf, 512.0, 2.87, 10, 10.0, args.nc_tol
-    dtf = 1e-2 if N <= 128 else 5e-3  # largest stable fine step (ARS(4,4,3)) of the grid
-    b0 = torch.from_numpy(initial_field(N, kz, 500000)).cuda()
+    w = nc_sweep_workload(args)
+    N, Rm, kz, P, T, tol, dtf = w["N"], w["Rm"], w["kz"], w["P"], w["T"], w["tol"], w["dtf"]
+    b0 = torch.from_numpy(initial_field(N, kz, w["seed"])).cuda()
     ctx = pd.Context(0)
-    ctx.set_problem("roberts", Rm, kz, N)
+    ctx.set_problem(w["flow"], Rm, kz, N)
     ctx.set_time(T, P, dtf, dtf, N)
-    ctx.set_scheme("rk443", "rk443")
+    ctx.set_scheme(w["scheme"], w["scheme"])
     u = b0[None].clone()
+    ctx.fine([0.0], u)  # warm-up (first launches)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for n in range(P):
@@ -408,9 +425,9 @@ def run_nc_sweep(args):
     uT = u[0].cpu().numpy()
     _log(f"# serial fine {serial_s:.3f} s, |b(T)| {np.linalg.norm(uT):.3e}")
     rows = []
-    for nc in (N // 8, N // 4, N // 2, N):
+    for nc in w["nc_list"]:
         errs = {}
-        for cand in (0.1, 0.05, 0.025, 0.0125, 0.00625, 0.003125):
+        for cand in w["dtc_cands"]:
             ctx.set_time(T, P, dtf, cand, nc)
             ctx.set_initial(b0)
             ctx.parareal(0.0, 0)
@@ -449,14 +466,15 @@ def run_nc_sweep(args):
         model = 1.0 / ((1.0 + k / P) * (tc / tf) + k / P) if k > 0 else None
         rows.append({"N_coarse": nc, "dt_coarse": dtc, "coarse_run_error": errs[dtc], "k_con": k,
                      "sigma": rep["sigma"][:rep["iters"]], "time_s": tp, "Rf_over_Rc": tf / tc,
-                     "speedup_vs_serial_gpu": serial_s / tp, "model_speedup_P10": model})
+                     "speedup_vs_serial_gpu": serial_s / tp, "model_speedup": model})
         _log(f"# N_C={nc} dt_c={dtc}: k_con {k}, {tp:.3f} s, Rf/Rc {tf / tc:.1f}, "
              f"speed-up {serial_s / tp:.2f} (model {model})")
     ctx.close()
-    print(json.dumps({"experiment": "coarse grid sweep", "flow": "roberts", "Rm": Rm, "kz": kz,
+    print(json.dumps({"experiment": "coarse grid sweep", "flow": w["flow"], "Rm": Rm, "kz": kz,
                       "N_coarse_list": [r["N_coarse"] for r in rows],
-                      "N_fine": N, "dt_fine": dtf, "slices": P, "T": T, "scheme": "rk443",
-                      "tol": tol, "serial_fine_gpu_s": serial_s, "rows": rows}), flush=True)
+                      "N_fine": N, "dt_fine": dtf, "slices": P, "T": T, "scheme": w["scheme"],
+                      "tol": tol, "model_processors": P,
+                      "serial_fine_gpu_s": serial_s, "rows": rows}), flush=True)
 
 
 def run_work_precision(args):
@@ -579,6 +597,8 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="learned versus plain coarse propagator (256^2, 128 slices)")
     ap.add_argument("--nc-sweep", action="store_true", help="coarse-grid sweep (Roberts Rm=512)")
+    ap.add_argument("--nc-sweep-gp", action="store_true",
+                    help="coarse-grid sweep on the headline workload (GP Rm=100, 128^2)")
     ap.add_argument("--nc-tol", type=float, default=1e-5, help="defect tolerance of the sweep")
     ap.add_argument("--nc-nf", type=int, default=128, help="fine grid of the sweep (128 or 256)")
     ap.add_argument("--work-precision", action="store_true", help="SBDF2 vs ARS(4,4,3) work-precision")
@@ -613,7 +633,7 @@ def main():
     if args.learned:
         run_learned(args)
         return
-    if args.nc_sweep:
+    if args.nc_sweep or args.nc_sweep_gp:
         run_nc_sweep(args)
         return
     if args.work_precision:
