@@ -156,6 +156,26 @@ pd_status pd_set_scheme(pd_ctx* ctx, pd_scheme fine, pd_scheme coarse);
 pd_status pd_set_initial(pd_ctx* ctx, const double* b0);
 pd_status pd_set_initial_dev(pd_ctx* ctx, const void* d_b0, void* hip_stream);
 
+/* Seeded initial field (the paper's random initial perturbation, Section 4;
+   amplitude and spectral extent are this library's choice): for each
+   component and every mode inside the 2/3 box with kx^2 + ky^2 <= kmax^2,
+   re and im = amp x a pair of normal deviates, every other mode zero; then
+   made solenoidal, b <- b - k (k.b)/|k|^2 with k = (kx, ky, kz).  The
+   deviates come from Philox4x32-10 (Salmon et al., SC 2011) keyed by `seed`
+   with counter (kx mod 2^32, ky mod 2^32, component, 0), turned into two
+   53-bit uniforms u1 = (j1 + 1) 2^-53, u2 = j2 2^-53 (j = (w_a >> 5) 2^26 +
+   (w_b >> 6) from words 0,1 and 2,3) and then into re = r cos(2 pi u2),
+   im = r sin(2 pi u2), r = sqrt(-2 ln u1) (Box-Muller), in plain IEEE double
+   arithmetic with the C library's log, sin and cos: the same bits as any
+   implementation of that recipe on the same host.
+   pd_seed_field writes the field for grid N and kz to out ([3][N][N]
+   complex, interleaved; host memory, caller owned; no device work);
+   PD_EINVAL for an invalid N, null out or non-finite arguments.
+   pd_seed_initial makes it the context's initial field U_0 (as
+   pd_set_initial; needs pd_set_time). */
+pd_status pd_seed_field(int N, double kz, uint64_t seed, double amp, double kmax, double* out);
+pd_status pd_seed_initial(pd_ctx* ctx, uint64_t seed, double amp, double kmax);
+
 /* Fine propagator F over one slice for `batch` independent fields:
    out[f] = F(in[f]) from time t0[f] (host array) to t0[f] + dT with dt_fine
    (n_f = dT/dt_fine steps; the fine propagator of Section 3).  in and out: device,
@@ -226,15 +246,39 @@ pd_status pd_set_slices(pd_ctx* ctx, const double* U, const double* Gold, int k)
    context's stream (0 on the single-workgroup path).  HIP events. */
 pd_status pd_profile_fine(pd_ctx* ctx, int reps, double* ms);
 
+/* The batched fine propagator F (Section 3: the fine solves of all slices run
+   in parallel) one step at a time, for measurement: runs fine steps
+   [step0, step0 + n_steps) of the fine sweep over all n_slices slices on the
+   context's working slice buffers, exactly the launches pd_parareal makes
+   (one column-phase and one row-phase kernel per step; SBDF2 fine stepper
+   only, else PD_EINVAL).  step0 = 0 starts the sweep from the current slice
+   states U_0..U_{P-1} (U itself is not changed); step0 > 0 continues a sweep
+   that the previous call on this context left at step0 (else PD_ESTATE);
+   step0 + n_steps <= dT/dt_fine.  Any other call that runs the fine
+   propagator on the slices ends the stepwise sweep.  ms (may be NULL):
+   ms[0] / ms[1] = summed durations of the column-phase / row-phase kernels,
+   ms[2] = duration of the whole n_steps, in milliseconds, from HIP events on
+   the context's stream.  Returns after the work completes. */
+pd_status pd_fine_sweep_steps(pd_ctx* ctx, int step0, int n_steps, double* ms);
+
+/* Working states of the fine propagator for slices [first, first + count),
+   full layout [count][3][N][N] in device memory: after pd_fine_sweep_steps
+   the slices' states after the steps run so far; after pd_parareal F(U_n) of
+   the last fine sweep (for the slices it ran). */
+pd_status pd_get_fine_states_dev(const pd_ctx* ctx, int first, int count, void* d_out,
+                                 void* hip_stream);
+
 /* Launch-shape autotuner for the fine step's two kernels.  The row-phase
    kernel has variants in values a lane (8 or 4) and waves a workgroup; the
    column-phase kernel in values a lane and columns a workgroup (which sets
    its LDS tile).  pd_autotune times every variant of both on this context's
    slice batch (reps back-to-back launches each, after one warm-up round; the
    inputs are the current slice states, which are left unchanged), selects the
-   fastest of each process-wide for this N, and returns their indices in
+   fastest of each for this context, and returns their indices in
    chosen[0] (rows), chosen[1] (columns) and their mean launch times in ms[0..1]
-   (either may be NULL).  With cache_path non-NULL the choice is first looked
+   (either may be NULL).  The choice belongs to this context (it applies to
+   its fine propagator calls, sweeps and pd_parareal until the next
+   pd_set_problem); other contexts keep theirs.  With cache_path non-NULL the choice is first looked
    up in that JSON file (key "<gfx arch>|<N>|<n_slices>"; ms = 0 on a hit) and
    stored there after timing.  Variants give identical results bitwise only
    with equal values a lane; all agree with the oracle to the parity bar. */
@@ -245,7 +289,8 @@ pd_status pd_autotune(pd_ctx* ctx, int reps, const char* cache_path, int* chosen
    and history with the row; columns: *a values a lane, *b columns a
    workgroup). */
 pd_status pd_variant_info(int N, int kind, int v, int* a, int* b);
-/* Select launch-shape variants for grid N process-wide (0, 0 = defaults). */
+/* Select the process-wide default launch-shape variants for grid N (0, 0 =
+   defaults), used by contexts and batches that were not autotuned. */
 pd_status pd_select_variant(int N, int rows_v, int cols_v);
 
 /* Slice-boundary states U_n, n = 0..n_slices, full layout [P+1][3][N][N]. */

@@ -21,7 +21,6 @@ is the same iteration and is what a learned linear coarse operator uses.
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -126,14 +125,3 @@ def speedup_bound(k_con: int, P: int, Rc_over_Rf: float) -> float:
 def efficiency(s: float, P: int) -> float:
     """Parallel efficiency s / P (Section 3.1)."""
     return s / P
-
-
-def is_stable(U, U0_norm: float, growth_cap: float, T: float) -> bool:
-    """Stability pre-check for a propagator run over [0, T]: every norm
-    finite and below 1e3 * ||U0|| * exp(growth_cap * T)."""
-    cap = 1e3 * U0_norm * math.exp(growth_cap * T)
-    for u in U:
-        v = norm2(u)
-        if not math.isfinite(v) or v > cap:
-            return False
-    return True

@@ -60,6 +60,8 @@ SYMBOLS = [
     "pd_lg_params", "pd_lg_set_params", "pd_lg_sample", "pd_lg_forward_sample", "pd_set_coarse",
     "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
     "pd_lg_load", "pd_set_pipeline", "pd_set_scheme", "pd_lg_set_loss_decay",
+    "pd_seed_field", "pd_seed_initial", "pd_fine_sweep_steps",
+    "pd_get_fine_states_dev",
 ]
 
 
@@ -151,6 +153,10 @@ def _load():
         "pd_set_pipeline": ([vp, i, i], i),
         "pd_set_scheme": ([vp, i, i], i),
         "pd_lg_set_loss_decay": ([vp, d], i),
+        "pd_seed_field": ([i, d, C.c_uint64, d, d, dp], i),
+        "pd_seed_initial": ([vp, C.c_uint64, d, d], i),
+        "pd_fine_sweep_steps": ([vp, i, i, dp], i),
+        "pd_get_fine_states_dev": ([vp, i, i, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -246,6 +252,11 @@ class Context:
                 raise ValueError(f"initial field must be [3, {self.N}, {self.N}]")
             self._ok(lib.pd_set_initial(self._h, _dptr(a.view(np.float64))))
 
+    def seed_initial(self, seed: int, amp: float = 1e-3, kmax: float = 4.0):
+        """Initial field from the library's seeded generator (the recipe of
+        ``synthetic.initial_field``, reproduced bit for bit)."""
+        self._ok(lib.pd_seed_initial(self._h, C.c_uint64(int(seed)), float(amp), float(kmax)))
+
     # -- propagators on device tensors --------------------------------------
     def _prop(self, fn, t0, x, out, *extra):
         import torch
@@ -340,9 +351,28 @@ class Context:
         self._ok(lib.pd_profile_fine(self._h, int(reps), _dptr(ms)))
         return float(ms[0]), float(ms[1]), float(ms[2])
 
+    def fine_sweep_steps(self, step0: int, n_steps: int, timed: bool = False):
+        """Fine steps [step0, step0 + n_steps) of the batched fine sweep over
+        all slices (step0 = 0 starts it from the slice states).  With timed,
+        returns (ms column kernels, ms row kernels, ms all) from HIP events."""
+        if not timed:
+            self._ok(lib.pd_fine_sweep_steps(self._h, int(step0), int(n_steps), None))
+            return None
+        ms = np.zeros(3, np.float64)
+        self._ok(lib.pd_fine_sweep_steps(self._h, int(step0), int(n_steps), _dptr(ms)))
+        return float(ms[0]), float(ms[1]), float(ms[2])
+
+    def get_fine_states_dev(self, first: int, count: int):
+        """Working states of the fine propagator, slices [first, first + count)."""
+        import torch
+        out = torch.empty((count, 3, self.N, self.N), dtype=torch.complex128, device="cuda")
+        self._ok(lib.pd_get_fine_states_dev(self._h, int(first), int(count),
+                                            C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
     def autotune(self, reps: int = 10, cache_path=None):
         """Pick the fastest launch shapes of the fine step's kernels for this
-        grid size; returns ((rows variant, cols variant), (ms rows, ms cols))."""
+        context (its grid and slice batch); returns ((rows variant, cols variant), (ms rows, ms cols))."""
         ch = (C.c_int * 2)()
         ms = np.zeros(2, np.float64)
         cp = cache_path.encode() if cache_path else None

@@ -27,6 +27,8 @@ struct pd_ctx {
   int coarse_form = PD_COARSE_AUTO;
   int scheme_f = PD_SCHEME_SBDF2;  // time steppers of F and G
   int scheme_c = PD_SCHEME_SBDF2;
+  int rows_v = -1, cols_v = -1;    // launch-shape variants chosen by pd_autotune (-1: process default)
+  int sweep_next = -1;             // pd_fine_sweep_steps: next step of the stepwise fine sweep
   // problem
   bool have_problem = false;
   int flow = PD_FLOW_NONE;
@@ -65,6 +67,11 @@ struct pd_ctx {
   } lg;
 
   size_t box_elems() const { return (size_t)3 * M * M; }
+  // a batch of fields on the fine grid with this context's launch shapes
+  void shapes(pd::FieldBatch& fb) const {
+    fb.rows_v = rows_v;
+    fb.cols_v = cols_v;
+  }
   size_t rows_elems() const { return (size_t)3 * M * N; }
 };
 

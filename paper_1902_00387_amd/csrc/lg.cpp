@@ -240,6 +240,7 @@ pd_status pd_lg_params(pd_ctx* c, float* out, size_t* n) {
 
 pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
   if (!c) return PD_EINVAL;
+  c->sweep_next = -1;
   c->err.clear();
   if (!c->lg.init) return fail(c, PD_ESTATE, "pd_lg_init not called");
   if (!c->have_initial) return fail(c, PD_ESTATE, "pd_set_initial not called");
@@ -303,6 +304,7 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
       fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
       fb.t0 = c->t0s.as<double>() + n0;
       fb.tw = c->tw.as<cplx>();
+      c->shapes(fb);
       if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
       PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
       sa.n0 = n0;

@@ -149,6 +149,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
         fb.T2 = c->T2f.as<cplx>() + (size_t)a * rows;
         fb.t0 = c->t0s.as<double>() + a;
         fb.tw = c->tw.as<cplx>();
+        c->shapes(fb);
         if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * a * box;
         int path = choose_path(c, b - a);
         if (path == PD_PATH_MULTI2) path = PD_PATH_MULTI;  // the chunks already use two streams

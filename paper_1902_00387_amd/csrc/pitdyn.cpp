@@ -212,6 +212,7 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
   }
   const pd::Problem pb = make_problem(c, dt, scheme);
   if (Ngrid == c->N) {
+    c->shapes(fb);
     PD_HIP(c, fine_batch(c, fb, pb, batch, nsteps, st), "propagate");
   } else {
     const int path = choose_path(c, batch);
@@ -336,6 +337,7 @@ pd_status pd_set_coarse_form(pd_ctx* c, pd_coarse_form f) {
 
 pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   if (!c) return PD_EINVAL;
+  c->sweep_next = -1;
   c->err.clear();
   if (flow != PD_FLOW_NONE && flow != PD_FLOW_ROBERTS && flow != PD_FLOW_GP)
     return fail(c, PD_EINVAL, "unknown flow %d", (int)flow);
@@ -348,6 +350,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
   c->T2f.release(); c->Uprev.release();
+  c->rows_v = c->cols_v = -1;
   c->flow = flow;
   c->Rm = Rm;
   c->kz = kz;
@@ -363,6 +366,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
 
 pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc) {
   if (!c) return PD_EINVAL;
+  c->sweep_next = -1;
   c->err.clear();
   if (!c->have_problem) return fail(c, PD_ESTATE, "pd_set_problem not called");
   if (!(T > 0) || !std::isfinite(T)) return fail(c, PD_EINVAL, "T must be positive");
@@ -493,6 +497,7 @@ pd_status pd_coarse_dev(pd_ctx* c, const double* t0, int batch, const void* d_in
 
 pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   if (!c) return PD_EINVAL;
+  c->sweep_next = -1;
   c->err.clear();
   if (!c->have_initial) return fail(c, PD_ESTATE, "pd_set_initial not called");
   if (max_iter < 0 || max_iter > PD_MAX_ITER) return fail(c, PD_EINVAL, "max_iter must be in [0, %d]", PD_MAX_ITER);
@@ -585,6 +590,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
     fb.t0 = c->t0s.as<double>() + n0;
     fb.tw = c->tw.as<cplx>();
+    c->shapes(fb);
     if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
     PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
     PD_HIP(c, hipEventRecord(ev[1], st), "event");
@@ -628,6 +634,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
 
 pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
   if (!c) return PD_EINVAL;
+  c->sweep_next = -1;
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (reps < 1 || !ms) return fail(c, PD_EINVAL, "reps must be >= 1 and ms non-null");
@@ -651,6 +658,7 @@ pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
   fb.T2 = c->T2f.as<cplx>();
   fb.t0 = c->t0s.as<double>();
   fb.tw = c->tw.as<cplx>();
+  c->shapes(fb);
   const pd::Problem pf = make_problem(c, c->dtf);
   float t = 0;
   // a whole fine sweep (all slices, every step) as Parareal launches it
@@ -679,6 +687,72 @@ pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
     PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
     ms[1] = t / reps;
   }
+  return PD_OK;
+}
+
+pd_status pd_fine_sweep_steps(pd_ctx* c, int step0, int n_steps, double* ms) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (c->scheme_f != PD_SCHEME_SBDF2) return fail(c, PD_EINVAL, "the fine stepper must be SBDF2");
+  if (step0 < 0 || n_steps < 1 || step0 + n_steps > c->nf)
+    return fail(c, PD_EINVAL, "steps [%d, %d) outside the slice's %d fine steps", step0,
+                step0 + n_steps, c->nf);
+  if (step0 > 0 && c->sweep_next != step0)
+    return fail(c, PD_ESTATE, "the fine sweep stands at step %d, not %d", c->sweep_next, step0);
+  DeviceGuard dg(c->device);
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems();
+  const int P = c->P;
+  pd::FieldBatch fb;
+  fb.B = c->Fo.as<cplx>();
+  fb.H = c->Hf.as<cplx>();
+  fb.T1 = c->T1f.as<cplx>();
+  fb.T2 = c->T2f.as<cplx>();
+  fb.t0 = c->t0s.as<double>();
+  fb.tw = c->tw.as<cplx>();
+  c->shapes(fb);
+  const pd::Problem pf = make_problem(c, c->dtf);
+  c->sweep_next = -1;
+  if (step0 == 0) {
+    PD_HIP(c, hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx),
+                             hipMemcpyDeviceToDevice, st), "copy");
+    PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
+  }
+  std::vector<hipEvent_t> ev;
+  struct EvFree {
+    std::vector<hipEvent_t>& e;
+    ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }
+  } evf{ev};
+  if (ms) {
+    ev.resize((size_t)2 * n_steps + 1, nullptr);
+    for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+  }
+  for (int s = step0; s < step0 + n_steps; ++s) {
+    const int i = s - step0;
+    PD_HIP(c, pd::cols(c->N, fb, pf, P, s, st), "cols");
+    if (ms) PD_HIP(c, hipEventRecord(ev[2 * i + 1], st), "event");
+    PD_HIP(c, pd::rows(c->N, fb, pf, P, s == 0 ? 1 : 2, 0, st), "rows");
+    if (ms) PD_HIP(c, hipEventRecord(ev[2 * i + 2], st), "event");
+  }
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  if (ms) {
+    double tc = 0.0, tr = 0.0;
+    for (int i = 0; i < n_steps; ++i) {
+      float a = 0.f, b = 0.f;
+      PD_HIP(c, hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]), "event");
+      PD_HIP(c, hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]), "event");
+      tc += a;
+      tr += b;
+    }
+    float all = 0.f;
+    PD_HIP(c, hipEventElapsedTime(&all, ev[0], ev[2 * n_steps]), "event");
+    ms[0] = tc;
+    ms[1] = tr;
+    ms[2] = all;
+  }
+  c->sweep_next = step0 + n_steps;
   return PD_OK;
 }
 
@@ -762,6 +836,7 @@ pd_status pd_select_variant(int N, int rows_v, int cols_v) {
 
 pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, double* ms) {
   if (!c) return PD_EINVAL;
+  c->sweep_next = -1;
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (reps < 1) return fail(c, PD_EINVAL, "reps must be >= 1");
@@ -769,8 +844,10 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   const int P = c->P;
   const std::string key = tune_key(c->device, c->N, P);
   int rv = 0, cv = 0;
-  if (cache_path && cache_lookup(cache_path, key, &rv, &cv) &&
-      pd::variant_select(c->N, rv, cv) == 0) {
+  if (cache_path && cache_lookup(cache_path, key, &rv, &cv) && rv >= 0 &&
+      rv < pd::variant_count(c->N, 0) && cv >= 0 && cv < pd::variant_count(c->N, 1)) {
+    c->rows_v = rv;
+    c->cols_v = cv;
     if (chosen) {
       chosen[0] = rv;
       chosen[1] = cv;
@@ -796,6 +873,8 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   const pd::Problem pf = make_problem(c, c->dtf);
   int cur_r = 0, cur_c = 0;
   pd::variant_current(c->N, &cur_r, &cur_c);
+  if (c->rows_v >= 0) cur_r = c->rows_v;
+  if (c->cols_v >= 0) cur_c = c->cols_v;
   // launches of the row (kind 0, an SBDF2 step) or column phase over nf
   // fields with batch variants (rows_v, cols_v)
   auto timed = [&](int kind, int nf, int rows_v, int cols_v, float* out) -> hipError_t {
@@ -836,7 +915,8 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   float best[2];
   int bestv[2];
   PD_HIP(c, tune(P, bestv, best), "autotune");
-  pd::variant_select(c->N, bestv[0], bestv[1]);
+  c->rows_v = bestv[0];
+  c->cols_v = bestv[1];
   if (chosen) {
     chosen[0] = bestv[0];
     chosen[1] = bestv[1];
@@ -858,6 +938,23 @@ pd_status pd_get_slices_dev(const pd_ctx* cc, void* d_out, void* s) {
   DeviceGuard dg(c->device);
   hipStream_t st = static_cast<hipStream_t>(s);
   PD_HIP(c, pd::unpack(c->U.as<cplx>(), static_cast<cplx*>(d_out), c->N, c->M, (size_t)c->P + 1, st), "unpack");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  return PD_OK;
+}
+
+pd_status pd_get_fine_states_dev(const pd_ctx* cc, int first, int count, void* d_out, void* s) {
+  pd_ctx* c = const_cast<pd_ctx*>(cc);
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  if (first < 0 || count < 0 || first + count > c->P)
+    return fail(c, PD_EINVAL, "slices [%d, %d) outside [0, %d)", first, first + count, c->P);
+  if (count == 0) return PD_OK;
+  if (!d_out) return fail(c, PD_EINVAL, "null pointer argument");
+  DeviceGuard dg(c->device);
+  hipStream_t st = static_cast<hipStream_t>(s);
+  PD_HIP(c, pd::unpack(c->Fo.as<cplx>() + (size_t)first * c->box_elems(), static_cast<cplx*>(d_out),
+                       c->N, c->M, (size_t)count, st), "unpack");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   return PD_OK;
 }

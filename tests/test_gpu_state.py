@@ -145,3 +145,16 @@ def test_report_speedup_model_matches_its_times(lib, chunks):
         ctx.set_initial(initial_field(N, 0.57, 41))
         r0 = ctx.parareal(tol, 0)
         assert r0["Rf_over_Rc"] == 0.0 and r0["model_speedup"] == 0.0
+
+
+@pytest.mark.parametrize("N,kz,seed,kmax", [(32, 0.57, 7, 4.0), (256, 1.1, 300017, 30.0)])
+def test_seed_initial_is_the_reference_field(lib, N, kz, seed, kmax):
+    """pd_seed_initial puts the generator's field bitwise into U_0."""
+    from synthetic import initial_field
+    with lib.Context(0) as ctx:
+        ctx.set_problem("gp", 50.0, kz, N)
+        ctx.set_time(1.0, 2, 0.05, 0.25, 0)
+        ctx.seed_initial(seed, 1e-3, kmax)
+        U0 = ctx.get_slices()[0]
+    ref = initial_field(N, kz, seed, amp=1e-3, kmax=kmax)
+    assert np.array_equal(U0.view(np.uint64), ref.view(np.uint64))

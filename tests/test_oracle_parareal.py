@@ -143,3 +143,27 @@ def test_speedup_model_respects_bound_and_limits():
     assert pr.speedup_model(3, 48, 0.0) == pytest.approx(16.0)
     assert pr.speedup_model(10, 10, 1e-2) < 1.0
     assert pr.efficiency(pr.speedup_model(3, 48, 0.0), 48) == pytest.approx(1 / 3)
+
+
+def test_speedup_model_hand_values_from_cost_decomposition():
+    """Eq. speed_up (Section 3.1) is the ratio of the serial fine cost P R_f
+    to the Parareal cost of one initial coarse run over all P slices plus k
+    iterations of one fine slice and one coarse slice each:
+    P R_c + k (R_f + R_c).  Hand-evaluated at nonzero R_c, so a swapped
+    coefficient (1 + P/k in place of 1 + k/P) or a dropped term fails."""
+    # P = 48, k = 3, R_f = 1, R_c = 0.01: 48 / (0.48 + 3 * 1.01) = 48 / 3.51
+    assert pr.speedup_model(3, 48, 0.01) == pytest.approx(48.0 / 3.51, rel=1e-14)
+    # P = 10, k = 4, R_f = 2, R_c = 0.5: 20 / (5 + 4 * 2.5) = 4/3
+    assert pr.speedup_model(4, 10, 0.25) == pytest.approx(4.0 / 3.0, rel=1e-14)
+    # P = 8, k = 8, R_c = R_f: 8 / (8 + 16) = 1/3 (Parareal with k = P loses)
+    assert pr.speedup_model(8, 8, 1.0) == pytest.approx(1.0 / 3.0, rel=1e-14)
+
+
+def test_speedup_model_reproduces_paper_gp_efficiency():
+    """Section 5.3: Galloway-Proctor Parareal converges in k_con = 3 with an
+    efficiency close to 0.3, near the 1/k_con bound.  The coarse solver there
+    has half the resolution in each direction and a 50 times larger step
+    (N_C = 256 vs N_F = 512, dt 5e-3 vs 1e-4), so R_c/R_f is about 1/200;
+    with about 50 slices the model gives an efficiency of about 0.3."""
+    s = pr.speedup_model(3, 50, 1.0 / 200.0)
+    assert 0.28 <= pr.efficiency(s, 50) <= 1.0 / 3.0
