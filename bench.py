@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: Parareal for the Galloway-Proctor kinematic dynamo on one MI355X.
+"""Benchmark: the batched fine propagator of Parareal for the Galloway-Proctor
+kinematic dynamo on one MI355X, on the largest single-GPU workload.
 
-Workload (one "step" = one whole Parareal solve, every stage of the path):
-  Galloway-Proctor CP flow, Rm = 100, kz = 0.57, 128 x 128 Fourier grid,
-  complex128, T = 64 cut into 64 slices; fine SBDF2 with dt = 2e-3 (500 steps a
-  slice, all 64 slices batched in every fine sweep); coarse SBDF2 on a 64 x 64
-  grid with dt = 1e-2 (the paper's N_C = N_F/2 with the largest stable step;
-  dt = 2e-2 blows up on 64 x 64); initial coarse run, Parareal iterations to a
-  defect sigma <= 1e-8, growth rate.  Seeded synthetic initial field.
+Workload (default): Galloway-Proctor CP flow, Rm = 2000, kz = 0.57, 512 x 512
+Fourier grid, complex128, T = 256 cut into 256 slices, fine SBDF2 with
+dt = 5e-4 (2000 steps a slice).  The slice states come from the library's
+seeded initial field and an initial coarse run.  One step = one fine time
+step of all 256 slices at once, exactly as every Parareal iteration launches
+it (column phase: inverse y-FFT, u x b, forward y-FFT with the 2/3 mask; row
+phase: forward x-FFT, 1/N^2, spectral curl, implicit diffusion solve, SBDF
+update, inverse x-FFT): 512^2 x 256 = 67.1 M mode-steps.
 
-value: serial-equivalent fine mode-steps per second of the whole solve,
-  N^2 * slices * (steps per slice) / (time per solve) -- the rate at which the
-  solve delivers the serial fine solution.  Inputs are resident in HBM before
-  the timed region.
+value: fine-propagator mode-steps per second, N^2 * slices * K / (time of K
+  steps); the states are resident in HBM before the timed region.
+roofline: 192 B per mode-step (read and write state and history, 3
+  complex128 components, full grid) over the mean duration of the step's two
+  kernels (HIP events on the stream they run on), against 8 TB/s.
+
+Other workloads: --config2 (a whole Parareal solve of the 128^2, 64-slice
+workload), --parareal5 (a Parareal solve of the default workload), --batch,
+--learned, --nc-sweep, --nc-sweep-gp, --table1, --work-precision.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -28,10 +35,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# the 128^2 whole-solve workload (--config2)
 N, KZ, RM, T, P = 128, 0.57, 100.0, 64.0, 64
 DT_FINE, DT_COARSE, N_COARSE = 2e-3, 1e-2, 64
 TOL, MAX_ITER, SEED = 1e-8, 64, 200000
+# the headline workload: largest single-GPU run
+N5, RM5, T5, P5, DT5, SEED5 = 512, 2000.0, 256.0, 256, 5e-4, 500000
+# coarse propagator of its initial coarse run (the slice states the steps
+# start from): SBDF2 on 64^2 with dt = 2.5e-3, stable over [0, 256]
+NC5, DTC5 = 64, 2.5e-3
+ALG_BYTES_PER_MODE_STEP = 192.0    # read + write b and H, 3 x complex128, full grid
 HBM_PEAK_GBS = 8000.0
+CPU_WORKERS_MAX = 16               # a one-GPU machine's share of host cores
 
 
 def box_m(n):
@@ -48,31 +63,51 @@ def kernel_bytes(n, fields):
     return cols, rows
 
 
-def cpu_baseline(budget_s=15.0):
-    """The FP64 oracle's fine propagator on a bounded sample of the workload:
-    whole slices (500 steps at 128^2) one after another until the budget is
-    spent; NumPy's FFT and array arithmetic run on one thread."""
+def _oracle_steps(job):
+    """One worker of the CPU baseline: the oracle's fine SBDF2 steps on one
+    seeded 512^2 field (no numerical input comes from the GPU)."""
+    seed, t0, nsteps = job
     from oracle import stepper
     from synthetic import initial_field
-    F = stepper.SliceSolver("gp", RM, KZ, N, T / P, DT_FINE)
-    b = initial_field(N, KZ, SEED)
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    b = initial_field(N5, KZ, seed, amp=1.0, kmax=40.0)
+    t = time.perf_counter()
+    stepper.propagate(b, "gp", RM5, KZ, t0, DT5, nsteps)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle's fine propagator, timed on the host's cores on a
+    bounded sample of the headline workload: one seeded 512^2 field per
+    worker process (as the paper's time-parallel layout gives each processor
+    its own slice), each advanced by the same number of fine steps, sized to
+    about `budget_s` of work a worker.  Runs before the GPU is touched (the
+    workers are forked)."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(ncpu, CPU_WORKERS_MAX))
+    per_step = _oracle_steps((SEED5 + 999, 0.0, 1))      # one step, also warms the caches
+    nsteps = max(2, min(400, int(budget_s / max(per_step, 1e-3))))
+    jobs = [(SEED5 + 1000 + w, float(w), nsteps) for w in range(workers)]
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        b = F(b, float(n))
-        n += 1
-        if time.perf_counter() - t0 >= budget_s or n >= P:
-            break
-    dt = time.perf_counter() - t0
-    steps = n * F.nsteps
-    return {"value": steps * N * N / dt, "unit": "fine mode-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n} of {P} slices x {F.nsteps} fine steps at {N}^2 "
-                      f"(serial, {dt:.1f} s)"}
+    with mp.get_context("fork").Pool(workers) as pool:
+        per = pool.map(_oracle_steps, jobs)
+    wall = time.perf_counter() - t0
+    done = workers * nsteps * N5 * N5
+    return {"value": done / wall, "unit": "fine mode-steps/s", "cores": workers,
+            "host_cpu_count": ncpu, "kind": "oracle",
+            "sample": f"{workers} worker processes x {nsteps} fine SBDF2 steps of one seeded "
+                      f"{N5}^2 field each (Rm={RM5:g}), {wall:.1f} s wall, "
+                      f"{min(per):.1f}-{max(per):.1f} s a worker; a whole slice is 2000 steps"}
 
 
 KERNEL_SOURCES = ("kernels.hip", "fft.hpp", "launch.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gp128_p64.json")
+TRAFFIC_FILE5 = os.path.join(ROOT, "profiles", "traffic_gp512_p256.json")
 
 
 def kernels_digest():
@@ -99,8 +134,10 @@ def summarize_pmc(fetch_csv, write_csv, out_path):
         return acc
     fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
     copy_bytes = float(1 << 30)
-    cf = max(v for k, vs in fetch.items() if "copyBuffer" in k for v in vs) * 1024.0
-    cw = max(v for k, vs in write.items() if "copyBuffer" in k for v in vs) * 1024.0
+    # the calibration copy is the program's last device copy (earlier copies
+    # are the library's own state copies)
+    cf = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs][-1] * 1024.0
+    cw = [v for k, vs in write.items() if "copyBuffer" in k for v in vs][-1] * 1024.0
     out = {"kernels_sha256_16": kernels_digest(), "fetch_scale": copy_bytes / cf,
            "write_scale": copy_bytes / cw, "kernels": {}}
     for name in fetch:
@@ -114,11 +151,11 @@ def summarize_pmc(fetch_csv, write_csv, out_path):
     return out
 
 
-def measured_traffic(kernel_prefix):
+def measured_traffic(kernel_prefix, path=TRAFFIC_FILE):
     """HBM bytes per launch of the kernel from the committed counter summary,
     or None if the summary is missing or the kernels changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -583,65 +620,17 @@ def run_table1(args):
     print(json.dumps({"experiment": "Table 1 growth rates", "T": 50.0, "rows": out}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="only the fine-sweep kernels (for profiler runs)")
-    ap.add_argument("--batch", action="store_true",
-                    help="the many-instance workload instead of the single solve")
-    ap.add_argument("--batch-scale", type=float, default=1.0)
-    ap.add_argument("--learned", action="store_true",
-                    help="learned versus plain coarse propagator (256^2, 128 slices)")
-    ap.add_argument("--nc-sweep", action="store_true", help="coarse-grid sweep (Roberts Rm=512)")
-    ap.add_argument("--nc-sweep-gp", action="store_true",
-                    help="coarse-grid sweep on the headline workload (GP Rm=100, 128^2)")
-    ap.add_argument("--nc-tol", type=float, default=1e-5, help="defect tolerance of the sweep")
-    ap.add_argument("--nc-nf", type=int, default=128, help="fine grid of the sweep (128 or 256)")
-    ap.add_argument("--work-precision", action="store_true", help="SBDF2 vs ARS(4,4,3) work-precision")
-    ap.add_argument("--table1", action="store_true", help="growth rates of the paper's Table 1 sets")
-    ap.add_argument("--table1-rows", default="", help="comma-separated row indices (default all)")
-    ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
-    ap.add_argument("--pipeline", type=int, default=-1,
-                    help="slice chunks of pipelined Parareal (0/1 off, -1 library default)")
-    ap.add_argument("--pipeline-spec", type=int, default=2,
-                    help="pipelined: 0 hold the last chunk, 1 start all early, 2 predict")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the HBM traffic summary from two rocprofv3 --pmc runs")
-    args = ap.parse_args()
-    if args.summarize_pmc:
-        print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_FILE)))
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
-              "path here is single-GPU (slices would shard across GPUs in contiguous blocks).", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run_config2(args):
+    """One step = one whole Parareal solve of the 128^2 workload: Galloway-
+    Proctor, Rm = 100, kz = 0.57, T = 64 over 64 slices, fine SBDF2 dt = 2e-3
+    (500 steps a slice, all slices batched), coarse SBDF2 on 64^2 with
+    dt = 1e-2 (the paper's N_C = N_F/2 with the largest stable step), initial
+    coarse run, iterations to sigma <= 1e-8, growth rate; value = serial-
+    equivalent fine mode-steps/s."""
     import torch
 
     import paper_1902_00387_amd as pd
     from synthetic import initial_field
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.batch:
-        run_batch(args)
-        return
-    if args.learned:
-        run_learned(args)
-        return
-    if args.nc_sweep or args.nc_sweep_gp:
-        run_nc_sweep(args)
-        return
-    if args.work_precision:
-        run_work_precision(args)
-        return
-    if args.table1:
-        run_table1(args)
-        return
     dev = torch.device("cuda:0")
     b0 = torch.from_numpy(initial_field(N, KZ, SEED)).to(dev)
     ctx = pd.Context(0)
@@ -718,7 +707,7 @@ def main():
     serial_s = time.perf_counter() - ts
 
     out = {
-        "metric": "fine-propagator mode-steps/sec (Parareal solve to sigma<=1e-8, serial-equivalent)",
+        "metric": "Parareal time-to-1e-8 as serial-equivalent fine mode-steps/sec (whole solve)",
         "value": value,
         "unit": "mode-steps/s",
         "n_gpus": 1,
@@ -771,10 +760,257 @@ def main():
                             "if the kernels changed since the counters were taken",
         },
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+
+
+def headline_context(pd, autotune=True):
+    """The headline workload's context: slice states from the library's
+    seeded initial field and an initial coarse run, launch shapes tuned on
+    the 256-slice batch."""
+    ctx = pd.Context(0)
+    ctx.set_problem("gp", RM5, KZ, N5)
+    ctx.set_time(T5, P5, DT5, DTC5, NC5)
+    ctx.seed_initial(SEED5, 1e-3, 4.0)
+    ctx.parareal(0.0, 0)
+    tuned = ctx.autotune(3) if autotune else None
+    return ctx, tuned
+
+
+def _sweep_chunks(step0, n, nf):
+    """(start, count) calls covering n fine steps from step0, restarting the
+    slice's sweep at step 0 when it reaches its end (nf steps)."""
+    out = []
+    s = step0 % nf
+    while n > 0:
+        c = min(n, nf - s)
+        out.append((s, c))
+        n -= c
+        s = (s + c) % nf
+    return out
+
+
+def run_headline(args, cpu):
+    """K fine steps of all 256 slices of the 512^2 workload (module header)."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    nf = int(round(T5 / P5 / DT5))
+    ctx, tuned = headline_context(pd)
+    (rv, cv), (mr, mc) = tuned
+    _log(f"# autotune: rows {pd.variants(N5, 0)[rv]} {mr*1e3:.0f} us, cols "
+         f"{pd.variants(N5, 1)[cv]} {mc*1e3:.0f} us")
+    if args.warmup > 0:
+        for a, c in _sweep_chunks(0, args.warmup, nf):
+            ctx.fine_sweep_steps(a, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = [0.0, 0.0, 0.0]
+    for a, c in _sweep_chunks(args.warmup, args.steps, nf):
+        m = ctx.fine_sweep_steps(a, c, timed=True)
+        ms = [x + y for x, y in zip(ms, m)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    K = args.steps
+    modes = N5 * N5 * P5
+    ms_cols, ms_rows = ms[0] / K, ms[1] / K
+    value = modes * K / elapsed
+    step_s = (ms_cols + ms_rows) * 1e-3
+    achieved = ALG_BYTES_PER_MODE_STEP * modes / step_s / 1e9
+    cols_b, rows_b = kernel_bytes(N5, P5)
+    rname = "k_rows<512,%d,%d,0,%s>" % (pd.variants(N5, 0)[rv][0], abs(pd.variants(N5, 0)[rv][1]),
+                                        "true" if pd.variants(N5, 0)[rv][1] < 0 else "false")
+    cname = "k_cols<512,%d,%d>" % tuple(pd.variants(N5, 1)[cv])
+    tr_c = measured_traffic("pd::" + cname, TRAFFIC_FILE5)
+    tr_r = measured_traffic("pd::" + rname, TRAFFIC_FILE5)
+    traffic = tr_c + tr_r if tr_c is not None and tr_r is not None else None
+    _log(f"# {K} steps: {elapsed*1e3/K:.3f} ms/step wall, kernels cols {ms_cols:.3f} + rows "
+         f"{ms_rows:.3f} ms; {value:.3e} mode-steps/s; {achieved:.0f} GB/s algorithmic")
+    out = {
+        "metric": "fine-propagator mode-steps/sec (batched F over all slices) & HBM GB/s",
+        "value": value, "unit": "mode-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic (library-seeded solenoidal field |k|<=4, amplitude 1e-3, "
+                "propagated by the initial coarse run)",
+        "config": {"workload": "Galloway-Proctor kinematic dynamo, Rm=2000, kz=0.57, 512x512 "
+                               "complex128, T=256 over 256 slices, fine SBDF2 dt=5e-4 (2000 "
+                               "steps a slice); one step = one fine step of all 256 slices",
+                   "N": N5, "slices": P5, "dt_fine": DT5, "fine_steps_per_slice": nf,
+                   "mode_steps_per_step": modes},
+        "roofline": {"bound": "hbm", "kernel": f"fine step: {cname} + {rname}",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "note": "achieved = 192 B x 67.1 M mode-steps / (mean column-phase + "
+                             "row-phase kernel duration); traffic = FETCH_SIZE + WRITE_SIZE of "
+                             "both kernels per step, scaled by the same counters on a 1 GiB "
+                             "copy (profiles/traffic_gp512_p256.json), null if the kernels "
+                             "changed since"},
+        "kernels": {
+            "cols": {"name": cname, "ms": ms_cols, "design_bytes": cols_b,
+                     "design_gbs": cols_b / (ms_cols * 1e-3) / 1e9},
+            "rows": {"name": rname, "ms": ms_rows, "design_bytes": rows_b,
+                     "design_gbs": rows_b / (ms_rows * 1e-3) / 1e9},
+            "design_bytes_per_mode_step": (cols_b + rows_b) / modes,
+        },
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_kernel_only5(args):
+    """For profiler runs: the headline's autotune and K fine steps of all
+    slices, then a plain 1 GiB device copy to calibrate byte counters."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    nf = int(round(T5 / P5 / DT5))
+    ctx, _ = headline_context(pd)
+    for a, c in _sweep_chunks(0, args.warmup + args.steps, nf):
+        ctx.fine_sweep_steps(a, c)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"kernel_only": True, "steps": args.warmup + args.steps,
+                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
+
+
+def run_parareal5(args):
+    """Parareal on the headline workload with the plain coarse propagator:
+    time to sigma <= 1e-8 (or the iterations run) against the serial fine
+    solve on the same GPU."""
+    import numpy as np
+    import torch
+
+    import paper_1902_00387_amd as pd
+    nc, dtc, iters = args.p5_nc, args.p5_dtc, args.p5_iters
+    ctx = pd.Context(0)
+    ctx.set_problem("gp", RM5, KZ, N5)
+    ctx.set_time(T5, P5, DT5, dtc, nc)
+    ctx.seed_initial(SEED5, 1e-3, 4.0)
+    ctx.parareal(0.0, 0)
+    ctx.autotune(3)
+    b0 = ctx.get_slices_dev()[0:1].clone()
+    # serial fine solve, slice after slice (batch 1)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    u = b0
+    norms = [float(torch.linalg.vector_norm(u).item())]
+    for n in range(P5):
+        u = ctx.fine([n * T5 / P5], u)
+        norms.append(float(torch.linalg.vector_norm(u).item()))
+        if n % 64 == 63:
+            _log(f"# serial fine: slice {n + 1}/{P5}, {time.perf_counter() - ts:.1f} s")
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - ts
+    g_serial = _growth(norms, T5 / P5)
+    ctx.seed_initial(SEED5, 1e-3, 4.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = ctx.parareal(TOL, iters)
+    gam = ctx.growth_rate()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    _log(f"# parareal N_C={nc} dt_c={dtc}: k_con {rep['k_con']} after {rep['iters']} iterations, "
+         f"{tp:.1f} s vs serial {serial_s:.1f} s")
+    ctx.close()
+    print(json.dumps({"experiment": "Parareal on the 512^2, 256-slice workload",
+                      "N_coarse": nc, "dt_coarse": dtc, "max_iter": iters, "k_con": rep["k_con"],
+                      "iters": rep["iters"], "sigma": rep["sigma"], "time_s": tp,
+                      "t_fine_s": rep["t_fine_s"], "t_coarse_s": rep["t_coarse_s"] + rep["t_coarse0_s"],
+                      "growth_rate": gam, "serial_fine_gpu_s": serial_s,
+                      "serial_growth_rate": g_serial, "speedup_vs_serial_gpu": serial_s / tp}),
+          flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config2", action="store_true",
+                    help="a whole Parareal solve of the 128^2, 64-slice workload as the step")
+    ap.add_argument("--parareal5", action="store_true",
+                    help="Parareal solves of the default workload (plain coarse propagator)")
+    ap.add_argument("--p5-nc", type=int, default=128, help="--parareal5: coarse grid")
+    ap.add_argument("--p5-dtc", type=float, default=2.5e-3, help="--parareal5: coarse step")
+    ap.add_argument("--p5-iters", type=int, default=8, help="--parareal5: iteration cap")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the fine-sweep kernels (for profiler runs)")
+    ap.add_argument("--batch", action="store_true",
+                    help="the many-instance workload instead of the single solve")
+    ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--learned", action="store_true",
+                    help="learned versus plain coarse propagator (256^2, 128 slices)")
+    ap.add_argument("--nc-sweep", action="store_true", help="coarse-grid sweep (Roberts Rm=512)")
+    ap.add_argument("--nc-sweep-gp", action="store_true",
+                    help="coarse-grid sweep on the headline workload (GP Rm=100, 128^2)")
+    ap.add_argument("--nc-tol", type=float, default=1e-5, help="defect tolerance of the sweep")
+    ap.add_argument("--nc-nf", type=int, default=128, help="fine grid of the sweep (128 or 256)")
+    ap.add_argument("--work-precision", action="store_true", help="SBDF2 vs ARS(4,4,3) work-precision")
+    ap.add_argument("--table1", action="store_true", help="growth rates of the paper's Table 1 sets")
+    ap.add_argument("--table1-rows", default="", help="comma-separated row indices (default all)")
+    ap.add_argument("--path", type=int, default=-1, help="fine launch path (-1 auto)")
+    ap.add_argument("--pipeline", type=int, default=-1,
+                    help="slice chunks of pipelined Parareal (0/1 off, -1 library default)")
+    ap.add_argument("--pipeline-spec", type=int, default=2,
+                    help="pipelined: 0 hold the last chunk, 1 start all early, 2 predict")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="write the HBM traffic summary from two rocprofv3 --pmc runs")
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
+              "path here is single-GPU (slices would shard across GPUs in contiguous blocks).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1902_00387_amd as pd  # noqa: F401  (loads the library; no GPU use yet)
+
+    default = not (args.batch or args.learned or args.nc_sweep or args.nc_sweep_gp or
+                   args.work_precision or args.table1 or args.config2 or args.parareal5 or
+                   args.kernel_only)
+    # the CPU baseline forks its workers before anything touches the GPU
+    cpu = cpu_baseline() if default and not args.no_cpu_baseline else None
+    if cpu is not None:
+        _log(f"# cpu baseline: {cpu['value']:.3e} mode-steps/s on {cpu['cores']} workers")
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch:
+        run_batch(args)
+        return
+    if args.learned:
+        run_learned(args)
+        return
+    if args.nc_sweep or args.nc_sweep_gp:
+        run_nc_sweep(args)
+        return
+    if args.work_precision:
+        run_work_precision(args)
+        return
+    if args.table1:
+        run_table1(args)
+        return
+    if args.config2:
+        run_config2(args)
+        return
+    if args.kernel_only:
+        run_kernel_only5(args)
+        return
+    if args.parareal5:
+        run_parareal5(args)
+        return
+    run_headline(args, cpu)
 
 
 if __name__ == "__main__":
