@@ -822,7 +822,8 @@ def run_headline(args, cpu):
     cols_b, rows_b = kernel_bytes(N5, P5)
     rname = "k_rows<512,%d,%d,0,%s>" % (pd.variants(N5, 0)[rv][0], abs(pd.variants(N5, 0)[rv][1]),
                                         "true" if pd.variants(N5, 0)[rv][1] < 0 else "false")
-    cname = "k_cols<512,%d,%d>" % tuple(pd.variants(N5, 1)[cv])
+    ce, ctx_ = pd.variants(N5, 1)[cv]
+    cname = ("k_cols<512,%d,%d>" % (ce, ctx_) if ctx_ > 0 else "k_cols_pf<512,%d,%d>" % (ce, -ctx_))
     tr_c = measured_traffic("pd::" + cname, TRAFFIC_FILE5)
     tr_r = measured_traffic("pd::" + rname, TRAFFIC_FILE5)
     traffic = tr_c + tr_r if tr_c is not None and tr_r is not None else None

@@ -362,21 +362,153 @@ __global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int 
                        RKS > 0 ? fb.R + 4 * f * box : nullptr);
 }
 
+// Workgroups are handed to the eight XCDs round-robin by linear block index.
+// When a column tile is narrower than a 128-byte line (TX < 8), the GL
+// workgroups whose tiles share lines are given block indices b, b + 8, ...,
+// so they run on one XCD and the line comes from HBM once (its L2 serves the
+// others).  Returns the logical (tile, field row) of this block.
+template <int TX>
+__device__ __forceinline__ void xcd_tile(int& tile, int& row) {
+  constexpr int GL = TX >= 8 ? 1 : 8 / TX;
+  const int nx = gridDim.x;
+  const int total = nx * gridDim.y;
+  const int b = blockIdx.x + blockIdx.y * nx;
+  int L = b;
+  if constexpr (GL > 1) {
+    if (b < total - total % (8 * GL)) {
+      const int xcd = b % 8, i = b / 8;
+      L = GL * (8 * (i / GL) + xcd) + i % GL;
+    }
+  }
+  tile = L % nx;
+  row = L / nx;
+}
+
 template <int N, int E, int TX, int MINW>
 __global__ __launch_bounds__(TX * (N / E))
 __attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb, int step,
                                                         int stage) {
   using G = Geo<N, E>;
   __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
-  if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
-  const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
+  int xt, row;
+  xcd_tile<TX>(xt, row);
+  if (fb.count != nullptr && row >= *fb.count) return;
+  const size_t f = fb.map != nullptr ? (size_t)fb.map[row] : (size_t)row;
   const size_t rows = (size_t)3 * G::M * N;
   // SBDF steps at t0 + step dt; Runge-Kutta stage `stage` at t0 + step dt + c dt
   const double t = stage == 0 ? fb.t0[f] + step * pb.dt
                               : fb.t0[f] + step * pb.dt + pb.rk_c[stage - 1] * pb.dt;
   const FlowPhase fp = flow_phase(pb, t);
-  col_tile<N, E, TX * G::T, E == 8 ? 8 : 4>(blockIdx.x * TX, tile, fb.T1 + f * rows,
+  col_tile<N, E, TX * G::T, E == 8 ? 8 : 4>(xt * TX, tile, fb.T1 + f * rows,
                                             fb.T2 + f * rows, fb.tw, fp);
+}
+
+// Persistent column phase: a grid sized to the chip's resident workgroups
+// loops over every (field, column tile) of the batch; while the groups
+// transform the tile staged in LDS, the lanes' loads of the next tile are
+// already in flight (held in registers), so the global-memory latency of one
+// tile overlaps the transforms of the previous one instead of adding to them.
+// Same arithmetic, in the same order, as col_tile.
+template <int N, int E, int TX>
+__global__ __launch_bounds__(TX * (N / E)) void k_cols_pf(FieldBatch fb, Problem pb, int step,
+                                                        int stage, int nfields) {
+  using G = Geo<N, E>;
+  constexpr int T = G::T, K = G::K, M = G::M;
+  constexpr int LANES = TX * T;
+  constexpr int TP = TX + 1, TS = M * TP;
+  constexpr int NTX = N / TX;  // column tiles a field
+  constexpr int NIT = (3 * M * TX + LANES - 1) / LANES;
+  static_assert(N % TX == 0, "column tiles must cover the grid");
+  __shared__ cplx tile[tile_elems<N, E>(LANES)];
+  const int nf = fb.count != nullptr ? *fb.count : nfields;
+  const int total = nf * NTX;
+  const size_t rows = (size_t)3 * M * N;
+  const int tid = threadIdx.x;
+  const int g = tid / T, j = tid % T;
+  cplx* s = tile + g * G::SPAN;
+  TwRegs<N, E> twr;
+  twr.load(j, fb.tw);
+  cplx buf[NIT];
+  auto field_of = [&](int t) -> size_t {
+    const int row = t / NTX;
+    return fb.map != nullptr ? (size_t)fb.map[row] : (size_t)row;
+  };
+  auto gload = [&](int t) {
+    const cplx* src = fb.T1 + field_of(t) * rows + (t % NTX) * TX;
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int i = tid + q * LANES;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      buf[q] = i < 3 * M * TX ? src[(c * M + r) * N + cc] : czero();
+    }
+  };
+  int t = blockIdx.x;
+  if (t < total) gload(t);
+  for (; t < total; t += gridDim.x) {
+    const size_t f = field_of(t);
+    const int x0 = (t % NTX) * TX;
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int i = tid + q * LANES;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      if (i < 3 * M * TX) tile[c * TS + r * TP + cc] = buf[q];
+    }
+    __syncthreads();
+    cplx w[3][E];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int ky = signed_k(j + T * e, N);
+        w[c][e] = (ky >= -K && ky <= K) ? tile[c * TS + (ky + K) * TP + g] : czero();
+      }
+    __syncthreads();
+    if (t + (int)gridDim.x < total) gload(t + gridDim.x);  // next tile, in flight meanwhile
+    // SBDF steps at t0 + step dt; Runge-Kutta stage `stage` at t0 + step dt + c dt
+    const double tt = stage == 0 ? fb.t0[f] + step * pb.dt
+                                 : fb.t0[f] + step * pb.dt + pb.rk_c[stage - 1] * pb.dt;
+    const FlowPhase fp = flow_phase(pb, tt);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft<N, E, 1>(w[c], s, j, twr);
+    const int x = x0 + g;
+    const double cx = fb.tw[x].re, sx = -fb.tw[x].im;
+    const double cxp = cx * fp.cpx - sx * fp.spx;   // cos(x + px)
+    const double sxp = sx * fp.cpx + cx * fp.spx;   // sin(x + px)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int m = j + T * e;
+      const double cy = fb.tw[m].re, sy = -fb.tw[m].im;
+      const double cyp = cy * fp.cpy - sy * fp.spy;  // cos(y + py)
+      const double syp = sy * fp.cpy + cy * fp.spy;  // sin(y + py)
+      const double ux = fp.amp * cyp, uy = fp.amp * sxp, uz = fp.amp * (cxp + syp);
+      const cplx bx = w[0][e], by = w[1][e], bz = w[2][e];
+      w[0][e] = csub(cscale(bz, uy), cscale(by, uz));
+      w[1][e] = csub(cscale(bx, uz), cscale(bz, ux));
+      w[2][e] = csub(cscale(by, ux), cscale(bx, uy));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, twr);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int ky = signed_k(j + T * e, N);
+        if (ky >= -K && ky <= K) tile[c * TS + (ky + K) * TP + g] = w[c][e];
+      }
+    __syncthreads();
+    cplx* dst = fb.T2 + f * rows + x0;
+#pragma unroll
+    for (int q = 0; q < NIT; ++q) {
+      const int i = tid + q * LANES;
+      const int c = i / (M * TX), rem = i - c * (M * TX);
+      const int r = rem / TX, cc = rem - r * TX;
+      if (i < 3 * M * TX) dst[(c * M + r) * N + cc] = tile[c * TS + r * TP + cc];
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,6 +1182,36 @@ static hipError_t launch_cols_v(const FieldBatch& fb, const Problem& pb, int nfi
   return hipGetLastError();
 }
 
+// Resident workgroups of a kernel on the current device (CUs x blocks a CU),
+// the grid of a persistent launch; per device and kernel, looked up once.
+template <class KernelT>
+static int resident_grid(KernelT kernel, int lanes) {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] > 0) return cached[dev];
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, lanes, 0) != hipSuccess || per < 1)
+    per = 1;
+  cached[dev] = cus * per;
+  return cached[dev];
+}
+
+template <int N, int E, int TX>
+static hipError_t launch_cols_pf(const FieldBatch& fb, const Problem& pb, int nfields, int step,
+                                 int stage, hipStream_t st) {
+  constexpr int T = N / E;
+  const int tiles = nfields * (N / TX);
+  const int res = resident_grid(k_cols_pf<N, E, TX>, TX * T);
+  const int grid = tiles < res ? tiles : res;
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL((k_cols_pf<N, E, TX>), dim3(grid), dim3(TX * T), 0, st, fb, pb, step, stage,
+                     nfields);
+  return hipGetLastError();
+}
+
 // ---- launch-shape variants and the per-size choice (autotuned) -----------
 using RowsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, int, hipStream_t);
 using ColsFn = hipError_t (*)(const FieldBatch&, const Problem&, int, int, int, hipStream_t);
@@ -1065,7 +1227,8 @@ struct ColsVariant {
 // Candidates: rows -- values a lane E (8 or 4), waves a workgroup W, W < 0 for
 // the form that loads the state and history with the row (faster on small
 // batches, fewer waves); columns -- values a lane E, columns a workgroup TX
-// (lanes <= 1024, LDS <= 160 KB).
+// (lanes <= 1024, LDS <= 160 KB), TX < 0 for the persistent form with |TX|
+// columns a tile.
 template <int N>
 struct Variants;
 template <>
@@ -1088,7 +1251,9 @@ struct Variants<64> {
   static constexpr ColsVariant cols[] = {{4, 32, launch_cols_v<64, 4, 32, 4>},
                                          {4, 16, launch_cols_v<64, 4, 16, 4>},
                                          {8, 32, launch_cols_v<64, 8, 32, 2>},
-                                         {8, 16, launch_cols_v<64, 8, 16, 2>}};
+                                         {8, 16, launch_cols_v<64, 8, 16, 2>},
+                                         {8, -16, launch_cols_pf<64, 8, 16>},
+                                         {4, -16, launch_cols_pf<64, 4, 16>}};
 };
 template <>
 struct Variants<128> {
@@ -1102,7 +1267,10 @@ struct Variants<128> {
                                          {4, 8, launch_cols_v<128, 4, 8, 4>},
                                          {8, 16, launch_cols_v<128, 8, 16, 2>},
                                          {8, 32, launch_cols_v<128, 8, 32, 2>},
-                                         {8, 8, launch_cols_v<128, 8, 8, 2>}};
+                                         {8, 8, launch_cols_v<128, 8, 8, 2>},
+                                         {8, -8, launch_cols_pf<128, 8, 8>},
+                                         {8, -16, launch_cols_pf<128, 8, 16>},
+                                         {4, -16, launch_cols_pf<128, 4, 16>}};
 };
 template <>
 struct Variants<256> {
@@ -1113,14 +1281,17 @@ struct Variants<256> {
   static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<256, 4, 16, 4>},
                                          {4, 8, launch_cols_v<256, 4, 8, 4>},
                                          {8, 16, launch_cols_v<256, 8, 16, 2>},
-                                         {8, 8, launch_cols_v<256, 8, 8, 2>}};
+                                         {8, 8, launch_cols_v<256, 8, 8, 2>},
+                                         {8, -8, launch_cols_pf<256, 8, 8>},
+                                         {4, -8, launch_cols_pf<256, 4, 8>}};
 };
 template <>
 struct Variants<512> {
   static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<512, 8, 1>},
                                          {8, 2, launch_rows_v<512, 8, 2>}};
   static constexpr ColsVariant cols[] = {{8, 8, launch_cols_v<512, 8, 8, 2>},
-                                         {8, 4, launch_cols_v<512, 8, 4, 2>}};
+                                         {8, 4, launch_cols_v<512, 8, 4, 2>},
+                                         {8, -4, launch_cols_pf<512, 8, 4>}};
 };
 
 static int size_slot(int N) {
