@@ -198,6 +198,24 @@ pd_status pd_step_coarse(pd_ctx* ctx, const double* t0, int batch, const double*
 pd_status pd_steps_dev(pd_ctx* ctx, const double* t0, int batch, double dt, int n_steps,
                        const void* d_in, void* d_out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   propagation as pd_steps_dev (same kernels and results, arguments and
+   errors), with its whole workspace -- compact state, SBDF history, the two
+   row buffers, the start times, the box-check flag and, for the Runge-Kutta
+   steppers, the stage sums -- in one static device array of 64 MiB per GPU,
+   held from library load to process end.  The caller passes inputs and
+   outputs; the call allocates nothing.  The workspace needs 96 M (M + N)
+   bytes a field (M = 2 floor((N-1)/3) + 1; 192 M^2 more with a Runge-Kutta
+   stepper) plus 8 a field and a few hundred bytes; a batch that does not
+   fit is PD_EINVAL with the sizes in pd_last_error (with SBDF2 at most 2
+   fields at N = 512, 9 at 256, 38 at 128, 151 at 64).
+   Every call on a GPU shares that GPU's workspace, which keeps the last
+   call's contents: calls that overlap on one GPU (from several threads or
+   contexts, or on several streams) race and must not be issued. */
+pd_status pd_steps_dev_noalloc(pd_ctx* ctx, const double* t0, int batch, double dt, int n_steps,
+                               const void* d_in, void* d_out, void* hip_stream);
+
 /* Parareal (Section 3): initial coarse run, then iterations
    U^k_{n+1} = F(U^{k-1}_n) + (G(U^k_n) - G(U^{k-1}_n)) until
    sigma_k = |U^k_P - U^{k-1}_P|_2 / |U^k_P|_2 <= tol or k = max_iter

@@ -61,7 +61,7 @@ SYMBOLS = [
     "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
     "pd_lg_load", "pd_set_pipeline", "pd_set_scheme", "pd_lg_set_loss_decay",
     "pd_seed_field", "pd_seed_initial", "pd_fine_sweep_steps",
-    "pd_get_fine_states_dev",
+    "pd_get_fine_states_dev", "pd_steps_dev_noalloc",
 ]
 
 
@@ -157,6 +157,7 @@ def _load():
         "pd_seed_initial": ([vp, C.c_uint64, d, d], i),
         "pd_fine_sweep_steps": ([vp, i, i, dp], i),
         "pd_get_fine_states_dev": ([vp, i, i, vp, vp], i),
+        "pd_steps_dev_noalloc": ([vp, dp, i, d, i, vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -281,6 +282,11 @@ class Context:
     def steps(self, t0, dt: float, n_steps: int, x, out=None):
         """n_steps steps of the fine scheme with size dt on the fine grid."""
         return self._prop(lib.pd_steps_dev, t0, x, out, C.c_double(dt), C.c_int(n_steps))
+
+    def steps_noalloc(self, t0, dt: float, n_steps: int, x, out=None):
+        """As steps(), with the library's static workspace (no allocation
+        inside the call; out must then be given to avoid one here)."""
+        return self._prop(lib.pd_steps_dev_noalloc, t0, x, out, C.c_double(dt), C.c_int(n_steps))
 
     # -- Parareal -----------------------------------------------------------
     def parareal(self, tol: float, max_iter: int):

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpitdyn.so")
 ARCH = os.environ.get("PITDYN_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "nn.hip", "pitdyn.cpp", "batch.cpp", "lg.cpp", "io.cpp", "pipeline.cpp", "seed.cpp"]
+SOURCES = ["kernels.hip", "nn.hip", "pitdyn.cpp", "batch.cpp", "lg.cpp", "io.cpp", "pipeline.cpp", "seed.cpp",
+           "static_ws.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = [

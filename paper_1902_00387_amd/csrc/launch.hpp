@@ -119,6 +119,9 @@ hipError_t sweep_conv_jobs(const SweepJob* d_jobs, int njobs, bool lds_resident,
 hipError_t pack(const cplx* full, cplx* box, int N, int M, size_t nfields, hipStream_t st);
 hipError_t unpack(const cplx* box, cplx* full, int N, int M, size_t nfields, hipStream_t st);
 hipError_t check_box(const cplx* full, int N, size_t nfields, int* dflag, hipStream_t st);
+// device address of the static fine-grid workspace on `device` (looked up
+// once per device; static_ws.hip)
+hipError_t scratch_resolve(int device);
 hipError_t norms2(const cplx* x, size_t len, int nfields, double* out, hipStream_t st);
 // Fo[f] = U[uidx[f]] for f = map[row], row < *count (rows = launch rows)
 hipError_t gather(const cplx* U, cplx* Fo, const int* uidx, const int* map, const int* count,

@@ -250,6 +250,10 @@ pd_status pd_create(pd_ctx** out, int hip_device) {
     return PD_EHIP;
   }
   c->stream = c->own;
+  // the static workspace of pd_steps_dev_noalloc: its device address on this
+  // device, looked up once per device here (the library's set-up call); a
+  // failed lookup is kept and reported by that call alone
+  (void)pd::scratch_resolve(hip_device);
   *out = c;
   return PD_OK;
 }
