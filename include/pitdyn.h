@@ -359,6 +359,19 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* ctx, int iters, int* n_stored);
    batch loss. */
 pd_status pd_lg_train(pd_ctx* ctx, int first, int count, int steps, int batch, double lr,
                       uint64_t seed, double* losses);
+/* Add n training samples given directly as network inputs and targets (host
+   arrays: features x[n][Q][12], targets r[n][Q][6], slice start times t[n];
+   Q = (2K+1)^2 box modes, the order and scaling pd_lg_sample reports).
+   *n_stored (may be NULL) receives the number of stored samples. */
+pd_status pd_lg_add_feature_samples(pd_ctx* ctx, int n, const float* x, const float* r,
+                                    const double* t, int* n_stored);
+/* Operand type of the network's matrix-core products: 0 (default) BF16,
+   the FP32 activations and weights rounded to nearest even at the operand
+   (v_mfma_f32_16x16x16_bf16); 1 FP32 operands unrounded
+   (v_mfma_f32_16x16x4_f32), a test mode that isolates the kernels' own
+   arithmetic from BF16 rounding.  Both accumulate in FP32.  Applies to every
+   later forward, gradient, training and learned-sweep call on ctx. */
+pd_status pd_lg_set_operands(pd_ctx* ctx, int fp32);
 /* Loss over stored samples [first, first + count). */
 pd_status pd_lg_loss(pd_ctx* ctx, int first, int count, double* loss);
 /* Gradient of the loss over samples [first, first + count) with respect to

@@ -75,27 +75,46 @@ def layer_weights(V_l: np.ndarray, t: np.ndarray) -> np.ndarray:
     return np.einsum("bj,jsio->bsio", phi, V_l)
 
 
-def forward(params: dict, x: np.ndarray, t: np.ndarray, Mf: int):
-    """c [B][Mf*Mf][6] and the cache for backward."""
+def bf16(a: np.ndarray) -> np.ndarray:
+    """The value the matrix-core kernels use for an FP32 operand in BF16
+    mode: the number rounded to FP32, then to the nearest BF16 (8 significant
+    bits, ties to even), returned as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(a):
+    return a
+
+
+def forward(params: dict, x: np.ndarray, t: np.ndarray, Mf: int, rnd=None):
+    """c [B][Mf*Mf][6] and the cache for backward.  rnd (default: none) is
+    applied to both operands of every channel-mixing product, to evaluate the
+    network with the operands the BF16 kernels use (``bf16``)."""
+    q = rnd if rnd is not None else _ident
     h = x @ params["W_in"]
     cache = {"x": x, "t": t, "hs": [h], "ys": []}
     L = params["V"].shape[0]
     for l in range(L):
-        W = layer_weights(params["V"][l], t)
+        W = q(layer_weights(params["V"][l], t))
         y = np.zeros_like(h)
         for s, (dy, dx) in enumerate(SHIFTS):
-            y += np.einsum("bmi,bio->bmo", shift_rows(h, Mf, dy, dx), W[:, s])
+            y += np.einsum("bmi,bio->bmo", q(shift_rows(h, Mf, dy, dx)), W[:, s])
         cache["ys"].append(y)
         h = h + params["gamma"][l][None] * y
         cache["hs"].append(h)
     return h @ params["W_out"], cache
 
 
-def loss_and_grad(params: dict, x, t, r, Mf: int, w=None):
+def loss_and_grad(params: dict, x, t, r, Mf: int, w=None, rnd=None):
     """Loss sum w_m |c - r|^2 / sum w_m |r|^2 (per-mode weights w, [Q]; None:
     all 1) and its gradients with respect to every parameter (manual
-    backward)."""
-    c, cache = forward(params, x, t, Mf)
+    backward).  rnd as in ``forward``, applied also to the operands of the
+    backward channel-mixing products."""
+    q = rnd if rnd is not None else _ident
+    c, cache = forward(params, x, t, Mf, rnd)
     wm = np.ones(c.shape[1]) if w is None else np.asarray(w, dtype=np.float64)
     diff = c - r
     den = float(np.sum(wm[None, :, None] * r * r))
@@ -113,14 +132,14 @@ def loss_and_grad(params: dict, x, t, r, Mf: int, w=None):
         h, y = cache["hs"][l], cache["ys"][l]
         grads["gamma"][l] = np.sum(dh * y, axis=0)
         dy = dh * params["gamma"][l][None]
-        W = layer_weights(params["V"][l], t)
+        W = q(layer_weights(params["V"][l], t))
         dh_prev = dh.copy()
         for s, (sy, sx) in enumerate(SHIFTS):
-            hs = shift_rows(h, Mf, sy, sx)
-            dWs = np.einsum("bmi,bmo->bio", hs, dy)                 # per sample
+            hs = q(shift_rows(h, Mf, sy, sx))
+            dWs = np.einsum("bmi,bmo->bio", hs, q(dy))              # per sample
             grads["V"][l, :, s] = np.einsum("bj,bio->jio", phi, dWs)
             # adjoint of the shift: contribution to h at m + s from y at m
-            dh_prev += shift_rows(np.einsum("bmo,bio->bmi", dy, W[:, s]), Mf, -sy, -sx)
+            dh_prev += shift_rows(np.einsum("bmo,bio->bmi", q(dy), W[:, s]), Mf, -sy, -sx)
         dh = dh_prev
     grads["W_in"] = np.einsum("bmi,bmo->io", cache["x"], dh)
     return loss, grads

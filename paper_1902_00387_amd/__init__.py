@@ -61,7 +61,8 @@ SYMBOLS = [
     "pd_step_fine", "pd_step_coarse", "pd_get_coarse_values", "pd_set_slices", "pd_lg_save",
     "pd_lg_load", "pd_set_pipeline", "pd_set_scheme", "pd_lg_set_loss_decay",
     "pd_seed_field", "pd_seed_initial", "pd_fine_sweep_steps",
-    "pd_get_fine_states_dev", "pd_steps_dev_noalloc",
+    "pd_get_fine_states_dev", "pd_steps_dev_noalloc", "pd_lg_add_feature_samples",
+    "pd_lg_set_operands",
 ]
 
 
@@ -158,6 +159,9 @@ def _load():
         "pd_fine_sweep_steps": ([vp, i, i, dp], i),
         "pd_get_fine_states_dev": ([vp, i, i, vp, vp], i),
         "pd_steps_dev_noalloc": ([vp, dp, i, d, i, vp, vp, vp], i),
+        "pd_lg_add_feature_samples": ([vp, i, C.POINTER(C.c_float), C.POINTER(C.c_float), dp,
+                                       C.POINTER(i)], i),
+        "pd_lg_set_operands": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -388,6 +392,23 @@ class Context:
     # -- learned coarse propagator -------------------------------------------
     def lg_init(self, layers: int = 4, seed: int = 0):
         self._ok(lib.pd_lg_init(self._h, int(layers), C.c_uint64(seed)))
+
+    def lg_add_feature_samples(self, x, r, t) -> int:
+        """Store samples given as network features x [n][Q][12], targets
+        r [n][Q][6] (float32) and slice start times t [n]; returns the number
+        of stored samples."""
+        xa = np.ascontiguousarray(np.asarray(x, np.float32))
+        ra = np.ascontiguousarray(np.asarray(r, np.float32))
+        ta = np.ascontiguousarray(np.asarray(t, np.float64))
+        n = C.c_int()
+        fp = C.POINTER(C.c_float)
+        self._ok(lib.pd_lg_add_feature_samples(self._h, int(ta.size), xa.ctypes.data_as(fp),
+                                               ra.ctypes.data_as(fp), _dptr(ta), C.byref(n)))
+        return n.value
+
+    def lg_set_operands(self, fp32: bool):
+        """Matrix-core operand type of the network: BF16 (default) or FP32."""
+        self._ok(lib.pd_lg_set_operands(self._h, 1 if fp32 else 0))
 
     def lg_set_loss_decay(self, beta: float):
         """Per-mode loss weights exp(-beta |k|^2 dT / Rm) (0: uniform)."""

@@ -64,6 +64,7 @@ struct pd_ctx {
     DevBuf Dn, gn, fn, nrm, uold;      // sweep and sample work (compact fine box)
     DevBuf wq;                         // [Q] per-mode loss weights (empty: uniform)
     bool weighted = false;
+    int f32ops = 0;                    // matrix-core operands: 0 BF16, 1 FP32 (test mode)
   } lg;
 
   size_t box_elems() const { return (size_t)3 * M * M; }

@@ -40,7 +40,9 @@ struct SplitMix {
 };
 
 pd::nn::Net net_of(pd_ctx* c, DevBuf& buf) {
-  return pd::nn::view(buf.as<float>(), c->lg.Q, c->lg.Mf, c->lg.L);
+  pd::nn::Net n = pd::nn::view(buf.as<float>(), c->lg.Q, c->lg.Mf, c->lg.L);
+  n.f32 = c->lg.f32ops;
+  return n;
 }
 
 // activation pointer tables for a batch of B
@@ -376,6 +378,44 @@ pd_status pd_lg_add_samples(pd_ctx* c, int n, const double* t0, const void* d_D,
          "copy");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   g.S += n;
+  return PD_OK;
+}
+
+pd_status pd_lg_add_feature_samples(pd_ctx* c, int n, const float* x, const float* r,
+                                    const double* t, int* n_stored) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->lg.init) return fail(c, PD_ESTATE, "pd_lg_init not called");
+  if (n < 1 || n > 65536 || !x || !r || !t) return fail(c, PD_EINVAL, "need 1..65536 samples and x, r, t");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(t[i])) return fail(c, PD_EINVAL, "t must be finite");
+  DeviceGuard dg(c->device);
+  hipStream_t st = c->stream;
+  auto& g = c->lg;
+  const size_t xq = (size_t)g.Q * 12, rq = (size_t)g.Q * 6;
+  pd_status s = grow(c, g.xs, sizeof(float) * xq * (g.S + n), sizeof(float) * xq * g.S, st);
+  if (s != PD_OK) return s;
+  s = grow(c, g.rs, sizeof(float) * rq * (g.S + n), sizeof(float) * rq * g.S, st);
+  if (s != PD_OK) return s;
+  s = grow(c, g.ts, sizeof(double) * (g.S + n), sizeof(double) * g.S, st);
+  if (s != PD_OK) return s;
+  PD_HIP(c, hipMemcpyAsync(g.xs.as<float>() + xq * g.S, x, sizeof(float) * xq * n,
+                           hipMemcpyHostToDevice, st), "copy");
+  PD_HIP(c, hipMemcpyAsync(g.rs.as<float>() + rq * g.S, r, sizeof(float) * rq * n,
+                           hipMemcpyHostToDevice, st), "copy");
+  PD_HIP(c, hipMemcpyAsync(g.ts.as<double>() + g.S, t, sizeof(double) * n, hipMemcpyHostToDevice, st),
+         "copy");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  g.S += n;
+  if (n_stored) *n_stored = g.S;
+  return PD_OK;
+}
+
+pd_status pd_lg_set_operands(pd_ctx* c, int fp32) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (fp32 != 0 && fp32 != 1) return fail(c, PD_EINVAL, "operand type must be 0 (BF16) or 1 (FP32)");
+  c->lg.f32ops = fp32;
   return PD_OK;
 }
 

@@ -8,7 +8,10 @@
 //   W_{l,s}(t) = V_{l,0,s} + cos t V_{l,1,s} + sin t V_{l,2,s},  s in {0, +kx, -kx, +ky, -ky}
 //   c = h_L W_out  (6 reals = 3 complex a mode)
 // and the learned coarse propagator is g + |D| c.  Activations are FP32 in
-// memory and rounded to BF16 as MFMA operands (v_mfma_f32_16x16x16_bf16).
+// memory and rounded to BF16 as MFMA operands (v_mfma_f32_16x16x16_bf16); a
+// test mode feeds the same FP32 values unrounded to the FP32 matrix
+// instruction (v_mfma_f32_16x16x4_f32, four per BF16 one: the K-slot of lane
+// group kb in instruction q is channel 4 kb + q), with the same accumulation.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -115,7 +118,26 @@ __global__ __launch_bounds__(256) void k_dense(const float* __restrict__ in, con
 // FWD:  y[m] = sum_s h[m + s] W_s(t);  out[m] = h[m] + gamma[m] * y[m]
 // BWD:  out[m] = dh[m] + sum_s (gamma * dh)[m - s] W_s(t)^T
 // W_s(t) is assembled in LDS (BF16) from the FP32 master V of layer l.
-template <bool BWD>
+// one 16 x 16 x 16 product step on the matrix cores: A[i][k] from lane (i,
+// kb) as a[r] = A[i][4 kb + r], B[k][j] as b[r] = B[4 kb + r][j]
+template <bool F32>
+__device__ __forceinline__ f32x4 mfma16(const float (&a)[4], const float (&b)[4], f32x4 acc) {
+  if constexpr (F32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q], acc, 0, 0, 0);
+    return acc;
+  } else {
+    bf16x4 ab, bb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ab[r] = f2bf(a[r]);
+      bb[r] = f2bf(b[r]);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab, bb, acc, 0, 0, 0);
+  }
+}
+
+template <bool BWD, bool F32>
 __global__ __launch_bounds__(256) void k_layer(const float* __restrict__ hin,
                                                const float* __restrict__ V,
                                                const double* __restrict__ tb,
@@ -123,7 +145,7 @@ __global__ __launch_bounds__(256) void k_layer(const float* __restrict__ hin,
                                                float* __restrict__ y_out, float* __restrict__ out,
                                                int Q, int Mf, const int* __restrict__ bidx) {
   constexpr int C = CH;
-  __shared__ short ws[5 * C * C];  // [s][k][j] (BWD: transposed)
+  __shared__ float ws[5 * C * C];  // [s][k][j] (BWD: transposed), FP32 (rounded at use)
   const int b = blockIdx.y;
   const double t = tb[bidx ? bidx[b] : b];
   const float ct = (float)cos(t), st = (float)sin(t);
@@ -134,7 +156,7 @@ __global__ __launch_bounds__(256) void k_layer(const float* __restrict__ hin,
     const int vi = BWD ? (j * C + k) : (k * C + j);
     const float w = V[(0 * 5 + s) * C * C + vi] + ct * V[(1 * 5 + s) * C * C + vi] +
                     st * V[(2 * 5 + s) * C * C + vi];
-    ws[i] = f2bf(w);
+    ws[i] = w;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -148,22 +170,22 @@ __global__ __launch_bounds__(256) void k_layer(const float* __restrict__ hin,
     const int ms = (m < Q) ? shifted(m, s, BWD ? -1 : 1, Mf) : -1;
 #pragma unroll
     for (int kc = 0; kc < 2; ++kc) {
-      bf16x4 a = {0, 0, 0, 0};
+      float a[4] = {0.f, 0.f, 0.f, 0.f};
       if (ms >= 0) {
         const float4 v = *reinterpret_cast<const float4*>(hin + (bo + ms) * C + 16 * kc + 4 * kb);
         float4 gv = {1.f, 1.f, 1.f, 1.f};
         if (BWD) gv = *reinterpret_cast<const float4*>(gamma + (size_t)ms * C + 16 * kc + 4 * kb);
-        a[0] = f2bf(v.x * gv.x);
-        a[1] = f2bf(v.y * gv.y);
-        a[2] = f2bf(v.z * gv.z);
-        a[3] = f2bf(v.w * gv.w);
+        a[0] = v.x * gv.x;
+        a[1] = v.y * gv.y;
+        a[2] = v.z * gv.z;
+        a[3] = v.w * gv.w;
       }
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
-        bf16x4 bv;
+        float bv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) bv[r] = ws[(s * C + 16 * kc + 4 * kb + r) * C + 16 * nt + li];
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[nt], 0, 0, 0);
+        acc[nt] = mfma16<F32>(a, bv, acc[nt]);
       }
     }
   }
@@ -188,6 +210,7 @@ __global__ __launch_bounds__(256) void k_layer(const float* __restrict__ hin,
 
 // dW_s(b)[i][o] = sum_m h[b][m + s][i] (gamma * dh)[b][m][o], one workgroup per
 // (sample, shift), one wave per 16 x 16 output tile, MFMA over 16-mode chunks.
+template <bool F32>
 __global__ __launch_bounds__(256) void k_dweight(const float* __restrict__ h,
                                                  const float* __restrict__ dh,
                                                  const float* __restrict__ gamma,
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(256) void k_dweight(const float* __restrict__ h,
   const size_t bo = (size_t)b * Q;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int m0 = 0; m0 < Q; m0 += 16) {
-    bf16x4 a, bv;
+    float a[4], bv[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = m0 + 4 * kb + r;
@@ -211,10 +234,10 @@ __global__ __launch_bounds__(256) void k_dweight(const float* __restrict__ h,
         const int o = 16 * ot + li;
         dv = dh[(bo + m) * C + o] * gamma[(size_t)m * C + o];
       }
-      a[r] = f2bf(av);
-      bv[r] = f2bf(dv);
+      a[r] = av;
+      bv[r] = dv;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc, 0, 0, 0);
+    acc = mfma16<F32>(a, bv, acc);
   }
   float* out = dW + ((size_t)b * 5 + s) * C * C;
 #pragma unroll
@@ -455,7 +478,8 @@ hipError_t forward(const Net& net, const float* x, const double* tb, const int* 
   hipLaunchKernelGGL((k_dense<12, CH>), dim3(grid1((size_t)B * Q)), dim3(256), 0, st, x,
                      net.W_in, h[0], Q, B, bidx);
   for (int l = 0; l < net.L; ++l) {
-    hipLaunchKernelGGL(k_layer<false>, dim3((Q + 63) / 64, B), dim3(256), 0, st, h[l],
+    auto kern = net.f32 ? k_layer<false, true> : k_layer<false, false>;
+    hipLaunchKernelGGL(kern, dim3((Q + 63) / 64, B), dim3(256), 0, st, h[l],
                        net.V + (size_t)l * 15 * CH * CH, tb, net.gamma + (size_t)l * Q * CH, y[l],
                        h[l + 1], Q, net.Mf, bidx);
   }
@@ -491,10 +515,12 @@ hipError_t backward(const Net& net, const float* x, const double* tb, const int*
     const float* gam = net.gamma + (size_t)l * Q * CH;
     hipLaunchKernelGGL(k_dgamma, dim3(grid1((size_t)Q * CH)), dim3(256), 0, st, dh, y[l],
                        gr.gamma + (size_t)l * Q * CH, Q, B);
-    hipLaunchKernelGGL(k_dweight, dim3(5, B), dim3(256), 0, st, h[l], dh, gam, w.dW, Q, net.Mf);
+    auto kdw = net.f32 ? k_dweight<true> : k_dweight<false>;
+    hipLaunchKernelGGL(kdw, dim3(5, B), dim3(256), 0, st, h[l], dh, gam, w.dW, Q, net.Mf);
     hipLaunchKernelGGL(k_dV, dim3(grid1(5 * CH * CH)), dim3(256), 0, st, w.dW, tb, bidx,
                        gr.V + (size_t)l * 15 * CH * CH, B);
-    hipLaunchKernelGGL(k_layer<true>, dim3((Q + 63) / 64, B), dim3(256), 0, st, dh,
+    auto kb = net.f32 ? k_layer<true, true> : k_layer<true, false>;
+    hipLaunchKernelGGL(kb, dim3((Q + 63) / 64, B), dim3(256), 0, st, dh,
                        net.V + (size_t)l * 15 * CH * CH, tb, gam, nullptr, dh2, Q, net.Mf, bidx);
     float* tmp = dh;
     dh = dh2;

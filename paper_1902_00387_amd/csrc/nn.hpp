@@ -15,6 +15,7 @@ constexpr int CH = 32;  // channels of the hidden layers
 //   W_in [12][CH] | V [L][3][5][CH][CH] | gamma [L][Q][CH] | W_out [CH][6]
 struct Net {
   int Q = 0, Mf = 0, L = 0;
+  int f32 = 0;  // matrix-core operands: 0 BF16 (rounded from FP32), 1 FP32
   float* W_in = nullptr;
   float* V = nullptr;
   float* gamma = nullptr;

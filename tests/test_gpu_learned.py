@@ -1,5 +1,6 @@
-"""GPU tests of the learned coarse propagator: BF16-MFMA forward and
-backward against the FP64 reference network, bitwise finite termination of
+"""GPU tests of the learned coarse propagator: the matrix-core forward and
+backward (FP32-operand test mode and BF16) against the FP64 reference network
+on host-made inputs, bitwise finite termination of
 learned-G Parareal, and the gain of the trained network over plain G."""
 import numpy as np
 import pytest
@@ -45,41 +46,81 @@ def small_ctx(lib, N=32, P=4, layers=2, seed=1):
     return ctx
 
 
+def _network_case(lib, ctx, N, L, beta, seed):
+    """Host-made network inputs (features, targets, slice times) and
+    trained-like parameters, stored in ctx; returns the FP64 views."""
+    Q = (2 * ((N - 1) // 3) + 1) ** 2
+    rng = np.random.default_rng(seed)
+    p = ctx.lg_params()
+    n_in, n_v = 12 * 32, L * 15 * 32 * 32
+    p[:n_in] = (rng.standard_normal(n_in) / np.sqrt(12.0)).astype(np.float32)
+    p[n_in:n_in + n_v] = (rng.standard_normal(n_v) * 0.3 / np.sqrt(160.0)).astype(np.float32)
+    p[n_in + n_v:-32 * 6] = (1.0 + 0.3 * rng.standard_normal(L * Q * 32)).astype(np.float32)
+    p[-32 * 6:] = (rng.standard_normal(32 * 6) * 0.2).astype(np.float32)
+    ctx.lg_set_params(p)
+    B = 4
+    x = rng.standard_normal((B, Q, 12)).astype(np.float32)
+    r = rng.standard_normal((B, Q, 6)).astype(np.float32)
+    t = np.array([0.0, 0.7, 2.1, 5.3])
+    assert ctx.lg_add_feature_samples(x, r, t) == B
+    K = (N - 1) // 3
+    ky, kx = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    dT, Rm, kz = 1.0 / 4, 50.0, 0.57
+    w = np.exp(-beta * (kx ** 2 + ky ** 2 + kz ** 2) * dT / Rm).ravel() if beta > 0 else None
+    return unflatten(p, Q, L), x.astype(np.float64), r.astype(np.float64), t, w, int(round(np.sqrt(Q)))
+
+
 @pytest.mark.parametrize("beta", [0.0, 4.0])
-def test_network_forward_and_gradients_match_fp64_reference(lib, beta):
-    """Forward and gradients of the loss (uniform, or weighted per mode by
-    exp(-beta |k|^2 dT / Rm)) against the FP64 reference network."""
+def test_network_fp32_operands_match_fp64_reference(lib, beta):
+    """FP32-operand mode of the matrix-core kernels: forward outputs and the
+    gradients of the (uniform or per-mode weighted) loss against the FP64
+    network on the same host inputs, to 1e-5 relative (FP32 accumulation)."""
     N, L = 32, 2
     with small_ctx(lib, N=N, layers=L) as ctx:
         ctx.lg_set_loss_decay(beta)
-        D = np.stack([initial_field(N, 0.57, 40 + i, amp=1.0, kmax=6) for i in range(4)])
-        ctx.lg_add_samples(np.array([0.0, 0.25, 0.5, 0.75]), dev(D))
-        rng = np.random.default_rng(0)
-        p = ctx.lg_params()
-        Q = (2 * ((N - 1) // 3) + 1) ** 2
-        # make every parameter group matter (trained-like values)
-        p[-32 * 6:] = (rng.standard_normal(32 * 6) * 0.2).astype(np.float32)
-        ctx.lg_set_params(p)
-        prm = unflatten(p, Q, L)
-        xs, rs, ts = zip(*[ctx.lg_sample(i) for i in range(4)])
-        x = np.stack(xs).astype(np.float64)
-        r = np.stack(rs).astype(np.float64)
-        t = np.array(ts)
-        Mf = int(round(np.sqrt(Q)))
+        ctx.lg_set_operands(True)
+        prm, x, r, t, w, Mf = _network_case(lib, ctx, N, L, beta, 3)
         c_ref, _ = onet.forward(prm, x, t, Mf)
         for i in range(4):
-            c_gpu = ctx.lg_forward_sample(i)
-            assert relnorm(c_gpu, c_ref[i]) <= 1e-2, (i, relnorm(c_gpu, c_ref[i]))
+            e = relnorm(ctx.lg_forward_sample(i), c_ref[i])
+            assert e <= 1e-5, (i, e)
         g_gpu, loss_gpu = ctx.lg_gradients(0, 4)
-        K = (N - 1) // 3
-        ky, kx = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
-        dT, Rm, kz = 1.0 / 4, 50.0, 0.57
-        w = np.exp(-beta * (kx ** 2 + ky ** 2 + kz ** 2) * dT / Rm).ravel() if beta > 0 else None
         loss_ref, g_ref = onet.loss_and_grad(prm, x, t, r, Mf, w)
-        assert abs(loss_gpu - loss_ref) <= 1e-2 * loss_ref
-        gg = unflatten(g_gpu, Q, L)
+        assert abs(loss_gpu - loss_ref) <= 1e-6 * loss_ref
+        gg = unflatten(g_gpu, (2 * ((N - 1) // 3) + 1) ** 2, L)
         for name in ("W_in", "V", "gamma", "W_out"):
-            assert relnorm(gg[name], g_ref[name]) <= 2e-2, (name, relnorm(gg[name], g_ref[name]))
+            e = relnorm(gg[name], g_ref[name])
+            print(f"fp32 operands, beta={beta}: {name} gradient rel. L2 {e:.2e}", flush=True)
+            assert e <= 1e-5, (name, e)
+
+
+@pytest.mark.parametrize("beta", [0.0, 4.0])
+def test_network_bf16_matches_fp64_on_rounded_operands(lib, beta):
+    """BF16 mode (the default) against the FP64 network evaluated with both
+    operands of every channel-mixing product rounded to BF16 the way the
+    kernels round them (FP32 value, nearest even); products and sums exact
+    in FP64 there, FP32-accumulated on the matrix cores.  A shift, transpose
+    or channel-tile mistake confined to a few modes moves the result by far
+    more than the 1e-4 bar."""
+    N, L = 32, 2
+    with small_ctx(lib, N=N, layers=L) as ctx:
+        ctx.lg_set_loss_decay(beta)
+        prm, x, r, t, w, Mf = _network_case(lib, ctx, N, L, beta, 4)
+        c_ref, _ = onet.forward(prm, x, t, Mf, rnd=onet.bf16)
+        c_exact, _ = onet.forward(prm, x, t, Mf)
+        for i in range(4):
+            e = relnorm(ctx.lg_forward_sample(i), c_ref[i])
+            # the rounding itself moves the output by far more than the bar
+            assert relnorm(c_exact[i], c_ref[i]) > 10 * max(e, 1e-5)
+            assert e <= 1e-4, (i, e)
+        g_gpu, loss_gpu = ctx.lg_gradients(0, 4)
+        loss_ref, g_ref = onet.loss_and_grad(prm, x, t, r, Mf, w, rnd=onet.bf16)
+        assert abs(loss_gpu - loss_ref) <= 1e-5 * loss_ref
+        gg = unflatten(g_gpu, (2 * ((N - 1) // 3) + 1) ** 2, L)
+        for name in ("W_in", "V", "gamma", "W_out"):
+            e = relnorm(gg[name], g_ref[name])
+            print(f"bf16 operands, beta={beta}: {name} gradient rel. L2 {e:.2e}", flush=True)
+            assert e <= 1e-4, (name, e)
 
 
 def test_learned_parareal_finite_termination_bitwise(lib):

@@ -75,3 +75,33 @@ def test_weighted_loss_closed_form():
     ref = np.sum((c[:, 7] - r[:, 7]) ** 2) / np.sum(r[:, 7] ** 2)
     l3, _ = net.loss_and_grad(p, x, t, r, Mf, w)
     assert abs(l3 - ref) <= 1e-14 * ref
+
+
+def test_bf16_rounding_pins():
+    """BF16 keeps 8 significant bits, rounding to nearest with ties to even."""
+    one = 1.0
+    cases = [(1.0, 1.0), (1 + 2.0 ** -8, 1.0), (1 + 3 * 2.0 ** -8, 1 + 2.0 ** -6),
+             (1 + 2.0 ** -7, 1 + 2.0 ** -7), (1 + 1.5 * 2.0 ** -7, 1 + 2.0 ** -6),
+             (-3.0, -3.0), (0.0, 0.0), (2.0 ** -130, 2.0 ** -130), (65504.0, 65536.0)]
+    for v, want in cases:
+        assert net.bf16(np.array([v]))[0] == want, (v, net.bf16(np.array([v]))[0], want)
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(10000) * 10.0 ** rng.uniform(-5, 5, 10000)
+    b = net.bf16(a)
+    assert np.all(np.abs(b - a) <= (2.0 ** -8 + 2.0 ** -23) * np.abs(a))
+    assert one == 1.0
+
+
+def test_rounded_operands_change_only_the_products():
+    """With rnd = identity the forward and gradients are the exact network;
+    with BF16 rounding they move by about the BF16 unit."""
+    p, x, t, r, Mf = tiny()
+    c0, _ = net.forward(p, x, t, Mf)
+    c1, _ = net.forward(p, x, t, Mf, rnd=lambda a: a)
+    assert np.array_equal(c0, c1)
+    c2, _ = net.forward(p, x, t, Mf, rnd=net.bf16)
+    d = np.linalg.norm(c2 - c0) / np.linalg.norm(c0)
+    assert 1e-5 < d < 2e-2
+    l0, g0 = net.loss_and_grad(p, x, t, r, Mf)
+    l2, g2 = net.loss_and_grad(p, x, t, r, Mf, rnd=net.bf16)
+    assert abs(l2 - l0) <= 2e-2 * l0
