@@ -863,6 +863,65 @@ def run_headline(args, cpu):
     print(json.dumps(out), flush=True)
 
 
+def run_c64(args):
+    """The complex64 variant of the 128^2 workload (and of the 512^2 one)
+    beside complex128: one batched fine step of all slices (HIP events over
+    the step's two kernels; complex64 moves half the bytes), and Parareal on
+    the 128^2 workload to the tolerance each number type can reach (1e-4 for
+    complex64, whose defect has an FP32 rounding floor near 2e-5 here; 1e-8
+    and 1e-4 for complex128)."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    from synthetic import initial_field
+    out = {"experiment": "complex64 variant", "fine_step": {}, "parareal_128": {}}
+    for (n, rm, T_, P_, dtf, dtc, nc, seed) in ((N, RM, T, P, DT_FINE, DT_COARSE, N_COARSE, SEED),
+                                               (N5, RM5, T5, P5, DT5, DTC5, NC5, SEED5)):
+        for prec in ("c128", "c64"):
+            ctx = pd.Context(0)
+            ctx.set_problem("gp", rm, KZ, n)
+            ctx.set_precision(prec)
+            ctx.set_time(T_, P_, dtf, dtc, nc)
+            ctx.set_initial(initial_field(n, KZ, seed))
+            ctx.parareal(0.0, 0)
+            ctx.fine_sweep_steps(0, 3)
+            ms = ctx.fine_sweep_steps(3, 20, timed=True)
+            step_ms = (ms[0] + ms[1]) / 20
+            m = box_m(n)
+            es = 16 if prec == "c128" else 8
+            design = es / 16.0 * 48 * (4 * m * n + 4 * m * m) / (n * n)
+            out["fine_step"][f"{n}_{prec}"] = {
+                "slices": P_, "ms_cols": ms[0] / 20, "ms_rows": ms[1] / 20,
+                "mode_steps_per_s": n * n * P_ / (step_ms * 1e-3),
+                "design_bytes_per_mode_step": design,
+                "design_gbs": design * n * n * P_ / (step_ms * 1e-3) / 1e9}
+            _log(f"# {n}^2 x {P_} {prec}: cols {ms[0]/20*1e3:.1f} + rows {ms[1]/20*1e3:.1f} us, "
+                 f"{n * n * P_ / (step_ms * 1e-3):.3e} mode-steps/s")
+            ctx.close()
+    b0 = initial_field(N, KZ, SEED)
+    for prec, tol in (("c128", TOL), ("c128", 1e-4), ("c64", 1e-4)):
+        ctx = pd.Context(0)
+        ctx.set_problem("gp", RM, KZ, N)
+        ctx.set_precision(prec)
+        ctx.set_time(T, P, DT_FINE, DT_COARSE, N_COARSE)
+        times = []
+        for _ in range(3):
+            ctx.set_initial(b0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = ctx.parareal(tol, MAX_ITER)
+            gam = ctx.growth_rate()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out["parareal_128"][f"{prec}_tol{tol:g}"] = {
+            "k_con": rep["k_con"], "sigma": rep["sigma"][:rep["iters"]], "time_s": min(times),
+            "growth_rate": gam}
+        _log(f"# parareal 128^2 {prec} tol {tol:g}: k_con {rep['k_con']}, {min(times)*1e3:.1f} ms, "
+             f"growth {gam:.6f}")
+        ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_kernel_only5(args):
     """For profiler runs: the headline's autotune and K fine steps of all
     slices, then a plain 1 GiB device copy to calibrate byte counters."""
@@ -940,6 +999,8 @@ def main():
                     help="a whole Parareal solve of the 128^2, 64-slice workload as the step")
     ap.add_argument("--parareal5", action="store_true",
                     help="Parareal solves of the default workload (plain coarse propagator)")
+    ap.add_argument("--c64", action="store_true",
+                    help="complex64 variant beside complex128 (fine step, 128^2 Parareal)")
     ap.add_argument("--p5-nc", type=int, default=128, help="--parareal5: coarse grid")
     ap.add_argument("--p5-dtc", type=float, default=2.5e-3, help="--parareal5: coarse step")
     ap.add_argument("--p5-iters", type=int, default=8, help="--parareal5: iteration cap")
@@ -981,7 +1042,7 @@ def main():
 
     default = not (args.batch or args.learned or args.nc_sweep or args.nc_sweep_gp or
                    args.work_precision or args.table1 or args.config2 or args.parareal5 or
-                   args.kernel_only)
+                   args.kernel_only or args.c64)
     # the CPU baseline forks its workers before anything touches the GPU
     cpu = cpu_baseline() if default and not args.no_cpu_baseline else None
     if cpu is not None:
@@ -1007,6 +1068,9 @@ def main():
         return
     if args.kernel_only:
         run_kernel_only5(args)
+        return
+    if args.c64:
+        run_c64(args)
         return
     if args.parareal5:
         run_parareal5(args)

@@ -97,6 +97,16 @@ typedef enum {
   PD_SCHEME_RK111 = 3   /* ARS(1,1,1) (RK111), forward-backward Euler */
 } pd_scheme;
 
+/* Number type of a context's fields and kernels.  The C ABI always takes and
+   returns complex128 fields; with PD_C64 the library rounds them to
+   complex64 on entry and computes the fine and coarse propagators, the
+   Parareal correction and the slice states in FP32 (defect and norm sums in
+   FP64), halving the bytes every step moves.  Set with pd_set_precision. */
+typedef enum {
+  PD_C128 = 0, /* complex128 (default) */
+  PD_C64 = 1   /* complex64 */
+} pd_prec;
+
 #define PD_MAX_ITER 256
 
 typedef struct {
@@ -130,6 +140,14 @@ pd_status pd_set_stream(pd_ctx* ctx, void* hip_stream);
 /* Problem: flow, Rm > 0, kz (any real), N in {16, 32, 64, 128, 256, 512}
    (Section 4: N x N Fourier modes).  Frees slice buffers of an earlier problem. */
 pd_status pd_set_problem(pd_ctx* ctx, pd_flow flow, double Rm, double kz, int N);
+
+/* Number type of the context (PD_C128 default, PD_C64).  Drops the time grid
+   and slice states (call pd_set_time again).  With PD_C64: SBDF2 steppers
+   only; coarse sweep in the convolution (N_coarse <= 64) or multi-launch
+   form; one launch shape per grid (pd_autotune is PD_EINVAL); the learned
+   coarse propagator, checkpoint/resume (pd_get_coarse_values,
+   pd_set_slices) and pd_steps_dev_noalloc are complex128 only (PD_EINVAL). */
+pd_status pd_set_precision(pd_ctx* ctx, pd_prec prec);
 
 /* Parareal time grid (Section 3): [0, T] cut into n_slices slices of length
    dT = T/n_slices; fine step dt_fine, coarse step dt_coarse on an N_coarse

@@ -62,7 +62,7 @@ SYMBOLS = [
     "pd_lg_load", "pd_set_pipeline", "pd_set_scheme", "pd_lg_set_loss_decay",
     "pd_seed_field", "pd_seed_initial", "pd_fine_sweep_steps",
     "pd_get_fine_states_dev", "pd_steps_dev_noalloc", "pd_lg_add_feature_samples",
-    "pd_lg_set_operands",
+    "pd_lg_set_operands", "pd_set_precision",
 ]
 
 
@@ -162,6 +162,7 @@ def _load():
         "pd_lg_add_feature_samples": ([vp, i, C.POINTER(C.c_float), C.POINTER(C.c_float), dp,
                                        C.POINTER(i)], i),
         "pd_lg_set_operands": ([vp, i], i),
+        "pd_set_precision": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -231,6 +232,11 @@ class Context:
         f = FLOWS[flow] if isinstance(flow, str) else int(flow)
         self._ok(lib.pd_set_problem(self._h, f, float(Rm), float(kz), int(N)))
         self.N = int(N)
+
+    def set_precision(self, prec: str):
+        """Number type of the context: "c128" (default) or "c64" (FP32
+        kernels; fields still enter and leave as complex128)."""
+        self._ok(lib.pd_set_precision(self._h, {"c128": 0, "c64": 1}[prec]))
 
     def set_time(self, T: float, n_slices: int, dt_fine: float, dt_coarse: float, N_coarse: int = 0):
         self._ok(lib.pd_set_time(self._h, float(T), int(n_slices), float(dt_fine),

@@ -11,6 +11,7 @@
 
 using pd::rt::DevBuf;
 using pd::cplx;
+using pd::cplxf;
 
 struct pd_ctx {
   int device = 0;
@@ -27,6 +28,7 @@ struct pd_ctx {
   int coarse_form = PD_COARSE_AUTO;
   int scheme_f = PD_SCHEME_SBDF2;  // time steppers of F and G
   int scheme_c = PD_SCHEME_SBDF2;
+  int prec = PD_C128;              // number type of the context's fields and kernels
   int rows_v = -1, cols_v = -1;    // launch-shape variants chosen by pd_autotune (-1: process default)
   int sweep_next = -1;             // pd_fine_sweep_steps: next step of the stepwise fine sweep
   // problem
@@ -43,6 +45,7 @@ struct pd_ctx {
   bool have_gold = false;              // the resumed state came with the previous coarse values
   // device memory
   DevBuf tw, twc;                      // twiddles (fine, coarse)
+  DevBuf twf, twcf;                    // the same in FP32 (complex64 variant)
   DevBuf U, Fo, Gold, Hf, T1f, T2f;    // slice buffers
   DevBuf Uprev, t0s;                   // defect copy, slice start times
   DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
@@ -68,8 +71,22 @@ struct pd_ctx {
   } lg;
 
   size_t box_elems() const { return (size_t)3 * M * M; }
+  // bytes of one complex value of the context's number type
+  size_t esize() const { return prec == PD_C64 ? sizeof(pd::cplxf) : sizeof(pd::cplx); }
+  // twiddle tables of the fine and coarse grid in the number type C
+  template <class C>
+  const C* twid() const {
+    if constexpr (sizeof(C) == sizeof(pd::cplxf)) return twf.as<C>();
+    else return tw.as<C>();
+  }
+  template <class C>
+  const C* twidc() const {
+    if constexpr (sizeof(C) == sizeof(pd::cplxf)) return twcf.as<C>();
+    else return twc.as<C>();
+  }
   // a batch of fields on the fine grid with this context's launch shapes
-  void shapes(pd::FieldBatch& fb) const {
+  template <class C>
+  void shapes(pd::FieldBatchT<C>& fb) const {
     fb.rows_v = rows_v;
     fb.cols_v = cols_v;
   }
@@ -111,6 +128,12 @@ hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb
 pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStream_t st);
 pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
                          int Ngrid, const void* d_in, void* d_out, hipStream_t st, int scheme);
+// the same two for a complex64 batch and sweep
+hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgsF& sa, const pd::Problem& pc, hipStream_t st);
+hipError_t fine_batch(pd_ctx* c, const pd::FieldBatchF& fb, const pd::Problem& pb, int nfields,
+                      int nsteps, hipStream_t st);
+// upload a host twiddle table (FP64 and its FP32 rounding)
+pd_status upload_twiddles(pd_ctx* c, int N, DevBuf& d64, DevBuf& d32, hipStream_t st);
 // learned coarse propagator (lg.cpp)
 void lg_release(pd_ctx* c);
 pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st);

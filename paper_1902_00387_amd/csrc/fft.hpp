@@ -1,4 +1,5 @@
-// Register/LDS complex FFT building blocks for gfx950 (FP64).
+// Register/LDS complex FFT building blocks for gfx950 (FP64, or FP32 for the
+// complex64 variant).
 //
 // A group of T = N/E lanes (E = 8 or 4) of one wavefront transforms one
 // length-N sequence.  Lane j holds E values in registers, v[e] = x[j + T*e]
@@ -13,33 +14,46 @@
 //
 // DIR = -1 is the forward transform X_k = sum_n x_n e^{-2 pi i nk/N},
 // DIR = +1 the unnormalised inverse.  Twiddles come from a table
-// tw[m] = e^{-2 pi i m/N} built on the host in extended precision.
+// tw[m] = e^{-2 pi i m/N} built on the host in extended precision.  Every
+// function works on complex128 (cplx) or complex64 (cplxf) values.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace pd {
 
-struct cplx {
-  double re, im;
+// Complex value of real type R (double: complex128 state, float: the
+// complex64 variant); re and im interleaved in memory.
+template <class R>
+struct cpx {
+  R re, im;
 };
+using cplx = cpx<double>;
+using cplxf = cpx<float>;
 
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+template <class R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <class R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 // a * conj(b)
-__device__ __forceinline__ cplx cmulc(cplx a, cplx b) {
+template <class R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
   return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
 }
 // multiply by DIR*i  (DIR = -1: by -i, DIR = +1: by +i)
-template <int DIR>
-__device__ __forceinline__ cplx mul_i(cplx a) {
+template <int DIR, class R>
+__device__ __forceinline__ cpx<R> mul_i(cpx<R> a) {
   if constexpr (DIR < 0) return {a.im, -a.re};
   else return {-a.im, a.re};
 }
 __device__ __forceinline__ cplx czero() { return {0.0, 0.0}; }
+template <class C>
+__device__ __forceinline__ C zero_of() { return {0, 0}; }
 
 // LDS index padding: one extra 16-byte slot every 2^PAD_SHIFT entries spreads
 // the power-of-two strides of the Stockham scatter over the 64 LDS banks
@@ -54,36 +68,37 @@ template <int N>
 __device__ __forceinline__ int lpad(int i) { return i + (i >> LdsSpan<N>::shift); }
 
 // ---- small DFTs in registers ---------------------------------------------
-template <int DIR>
-__device__ __forceinline__ void dft2(cplx& a, cplx& b) {
-  cplx t = a;
+template <int DIR, class C>
+__device__ __forceinline__ void dft2(C& a, C& b) {
+  C t = a;
   a = cadd(t, b);
   b = csub(t, b);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft4(cplx& x0, cplx& x1, cplx& x2, cplx& x3) {
-  cplx t0 = cadd(x0, x2), t1 = csub(x0, x2);
-  cplx t2 = cadd(x1, x3), t3 = mul_i<DIR>(csub(x1, x3));
+template <int DIR, class C>
+__device__ __forceinline__ void dft4(C& x0, C& x1, C& x2, C& x3) {
+  C t0 = cadd(x0, x2), t1 = csub(x0, x2);
+  C t2 = cadd(x1, x3), t3 = mul_i<DIR>(csub(x1, x3));
   x0 = cadd(t0, t2);
   x2 = csub(t0, t2);
   x1 = cadd(t1, t3);
   x3 = csub(t1, t3);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft8(cplx* x) {
+template <int DIR, class C>
+__device__ __forceinline__ void dft8(C* x) {
+  using R = decltype(x->re);
   // split into even / odd halves, two radix-4 DFTs, then combine with
   // w8^k = e^{DIR 2 pi i k/8}
-  cplx e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
-  cplx o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  C e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  C o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
   dft4<DIR>(e0, e1, e2, e3);
   dft4<DIR>(o0, o1, o2, o3);
-  constexpr double h = 0.70710678118654752440;  // sqrt(2)/2
+  constexpr R h = (R)0.70710678118654752440;  // sqrt(2)/2
   // w8^1 = h (1 + DIR i), w8^2 = DIR i, w8^3 = h (-1 + DIR i)
-  cplx w1o1 = {h * (o1.re - DIR * o1.im), h * (o1.im + DIR * o1.re)};
-  cplx w2o2 = mul_i<DIR>(o2);
-  cplx w3o3 = {h * (-o3.re - DIR * o3.im), h * (-o3.im + DIR * o3.re)};
+  C w1o1 = {h * (o1.re - DIR * o1.im), h * (o1.im + DIR * o1.re)};
+  C w2o2 = mul_i<DIR>(o2);
+  C w3o3 = {h * (-o3.re - DIR * o3.im), h * (-o3.im + DIR * o3.re)};
   x[0] = cadd(e0, o0);
   x[4] = csub(e0, o0);
   x[1] = cadd(e1, w1o1);
@@ -94,8 +109,8 @@ __device__ __forceinline__ void dft8(cplx* x) {
   x[7] = csub(e3, w3o3);
 }
 
-template <int R, int DIR>
-__device__ __forceinline__ void dftR(cplx* x) {
+template <int R, int DIR, class C>
+__device__ __forceinline__ void dftR(C* x) {
   if constexpr (R == 2) dft2<DIR>(x[0], x[1]);
   else if constexpr (R == 4) dft4<DIR>(x[0], x[1], x[2], x[3]);
   else dft8<DIR>(x);
@@ -138,12 +153,12 @@ struct Plan {
 // the table and then kept in registers (forward convention e^{-2 pi i m/N};
 // the inverse uses their conjugates).  Loading them ahead keeps global-memory
 // latency out of the passes, which the LDS exchange orders.
-template <int N, int E>
+template <int N, int E, class C = cplx>
 struct TwRegs {
   using PL = Plan<N, E>;
   static constexpr int count = PL::tw_total();
-  cplx w[count > 0 ? count : 1];
-  __device__ __forceinline__ void load(int j, const cplx* __restrict__ tw) {
+  C w[count > 0 ? count : 1];
+  __device__ __forceinline__ void load(int j, const C* __restrict__ tw) {
     constexpr int T = N / E;
     int o = 0;
 #pragma unroll
@@ -167,19 +182,19 @@ struct TwRegs {
 // pass (NS * R = N) output k of butterfly b lands at b + k*NS = j + T*(q +
 // Q*k), which is the lane's own strided register q + Q*k: the butterfly runs
 // in place in registers and the pass needs no exchange.
-template <int N, int E, int R, int NS, int DIR>
-__device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* wl) {
+template <int N, int E, int R, int NS, int DIR, class C>
+__device__ __forceinline__ void fft_pass(C* v, C* s, int j, const C* wl) {
   constexpr int T = N / E, Q = E / R;
   if constexpr (NS * R == N) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      cplx x[R];
+      C x[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) x[k] = v[q + k * Q];
       if constexpr (NS > 1) {
 #pragma unroll
         for (int k = 1; k < R; ++k) {
-          const cplx w = wl[q * (R - 1) + k - 1];
+          const C w = wl[q * (R - 1) + k - 1];
           x[k] = (DIR < 0) ? cmul(x[k], w) : cmulc(x[k], w);
         }
       }
@@ -193,13 +208,13 @@ __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* wl
   for (int q = 0; q < Q; ++q) {
     const int b = j + T * q;
     const int jj = b & (NS - 1);
-    cplx x[R];
+    C x[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) x[k] = v[q + k * Q];
     if constexpr (NS > 1) {
 #pragma unroll
       for (int k = 1; k < R; ++k) {
-        const cplx w = wl[q * (R - 1) + k - 1];
+        const C w = wl[q * (R - 1) + k - 1];
         x[k] = (DIR < 0) ? cmul(x[k], w) : cmulc(x[k], w);
       }
     }
@@ -214,8 +229,8 @@ __device__ __forceinline__ void fft_pass(cplx* v, cplx* s, int j, const cplx* wl
   group_sync();
 }
 
-template <int N, int E, int P, int DIR>
-__device__ __forceinline__ void fft_from(cplx* v, cplx* s, int j, const cplx* w) {
+template <int N, int E, int P, int DIR, class C>
+__device__ __forceinline__ void fft_from(C* v, C* s, int j, const C* w) {
   using PL = Plan<N, E>;
   if constexpr (P < PL::passes) {
     fft_pass<N, E, PL::R(P), PL::NS(P), DIR>(v, s, j, w);
@@ -226,15 +241,15 @@ __device__ __forceinline__ void fft_from(cplx* v, cplx* s, int j, const cplx* w)
 // Full length-N transform of the strided register vector v (E values a
 // lane, T = N/E lanes, all in one wavefront; see header).  s: this group's
 // LDS span (LdsSpan<N>::value entries); t: the lane's twiddles (TwRegs).
-template <int N, int E, int DIR>
-__device__ __forceinline__ void fft(cplx* v, cplx* s, int j, const TwRegs<N, E>& t) {
+template <int N, int E, int DIR, class C>
+__device__ __forceinline__ void fft(C* v, C* s, int j, const TwRegs<N, E, C>& t) {
   fft_from<N, E, 0, DIR>(v, s, j, t.w);
 }
 
 // Same, reading the lane's twiddles from the table first.
-template <int N, int E, int DIR>
-__device__ __forceinline__ void fft(cplx* v, cplx* s, int j, const cplx* __restrict__ tw) {
-  TwRegs<N, E> t;
+template <int N, int E, int DIR, class C>
+__device__ __forceinline__ void fft(C* v, C* s, int j, const C* __restrict__ tw) {
+  TwRegs<N, E, C> t;
   t.load(j, tw);
   fft_from<N, E, 0, DIR>(v, s, j, t.w);
 }

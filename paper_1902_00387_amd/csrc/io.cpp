@@ -79,6 +79,7 @@ pd_status pd_get_coarse_values(const pd_ctx* cc, double* out) {
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (!out) return fail(c, PD_EINVAL, "null pointer argument");
+  if (c->prec == PD_C64) return fail(c, PD_EINVAL, "checkpoints are complex128 only");
   DeviceGuard dg(c->device);
   const size_t full = (size_t)3 * c->N * c->N;
   DevBuf tmp;
@@ -96,6 +97,7 @@ pd_status pd_set_slices(pd_ctx* c, const double* U, const double* Gold, int k) {
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (!U) return fail(c, PD_EINVAL, "null pointer argument");
   if (k < 0 || k >= PD_MAX_ITER) return fail(c, PD_EINVAL, "k must be in [0, %d)", PD_MAX_ITER);
+  if (c->prec == PD_C64) return fail(c, PD_EINVAL, "checkpoints are complex128 only");
   DeviceGuard dg(c->device);
   pd_status s = host_to_box(c, U, (size_t)c->P + 1, c->U.as<cplx>());
   if (s != PD_OK) return s;

@@ -112,17 +112,18 @@ __device__ __forceinline__ cplx rk_update(cplx nl, double L, double d, double dt
 // mode 0: start of a slice (inverse transform of the state only);
 // mode 1: SBDF1 update; mode 2: SBDF2 update; RKS = j > 0 (mode ROW_RK + j):
 // end of Runge-Kutta stage j (stage sums in R).  last: skip the inverse.
-template <int N, int E, int RKS = 0, bool PF = false>
-__device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cplx* __restrict__ B,
-                                          cplx* __restrict__ H, const cplx* __restrict__ T2,
-                                          cplx* __restrict__ T1, const cplx* __restrict__ tw,
+template <int N, int E, int RKS = 0, bool PF = false, class C = cplx>
+__device__ __forceinline__ void row_phase(int r, bool active, int j, C* s, C* __restrict__ B,
+                                          C* __restrict__ H, const C* __restrict__ T2,
+                                          C* __restrict__ T1, const C* __restrict__ tw,
                                           const Problem& pb, int mode, bool last,
-                                          cplx* __restrict__ R = nullptr) {
+                                          C* __restrict__ R = nullptr) {
   using G = Geo<N, E>;
+  using Rl = decltype(C::re);  // FP64, or FP32 for the complex64 variant
   constexpr int T = G::T, K = G::K, M = G::M;
-  TwRegs<N, E> twr;
+  TwRegs<N, E, C> twr;
   twr.load(j, tw);
-  cplx w[3][E];
+  C w[3][E];
   const int ky = r - K;
   if (mode == 0) {
 #pragma unroll
@@ -130,7 +131,7 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int kx = signed_k(j + T * e, N);
-        w[c][e] = (active && kx >= -K && kx <= K) ? B[(c * M + r) * M + kx + K] : czero();
+        w[c][e] = (active && kx >= -K && kx <= K) ? B[(c * M + r) * M + kx + K] : zero_of<C>();
       }
   } else {
     // all three components' loads are issued before the first transform;
@@ -139,9 +140,9 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int e = 0; e < E; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : czero();
+      for (int e = 0; e < E; ++e) w[c][e] = active ? T2[(c * M + r) * N + j + T * e] : zero_of<C>();
     constexpr bool PRE = PF && RKS == 0;
-    cplx bo[3][PRE ? E : 1], ho[3][PRE ? E : 1];
+    C bo[3][PRE ? E : 1], ho[3][PRE ? E : 1];
     if constexpr (PRE) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -150,23 +151,23 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const int idx = (c * M + r) * M + kx + K;
-          bo[c][e] = in ? B[idx] : czero();
-          ho[c][e] = (in && mode != 1) ? H[idx] : czero();
+          bo[c][e] = in ? B[idx] : zero_of<C>();
+          ho[c][e] = (in && mode != 1) ? H[idx] : zero_of<C>();
         }
       }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) fft<N, E, -1>(w[c], s, j, twr);
-    const double sc = 1.0 / ((double)N * (double)N);
-    const double dt = pb.dt, kz = pb.kz;
+    const Rl sc = (Rl)(1.0 / ((double)N * (double)N));
+    const Rl dt = (Rl)pb.dt, kz = (Rl)pb.kz;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int kx = signed_k(j + T * e, N);
       if (active && kx >= -K && kx <= K) {
-        const cplx ex = cscale(w[0][e], sc), ey = cscale(w[1][e], sc), ez = cscale(w[2][e], sc);
+        const C ex = cscale(w[0][e], sc), ey = cscale(w[1][e], sc), ez = cscale(w[2][e], sc);
         // i k x E with k = (kx, ky, kz)
-        const double dkx = kx, dky = ky;
-        cplx nl[3];
+        const Rl dkx = kx, dky = ky;
+        C nl[3];
         nl[0] = mul_i<1>(csub(cscale(ez, dky), cscale(ey, kz)));
         nl[1] = mul_i<1>(csub(cscale(ex, kz), cscale(ez, dkx)));
         nl[2] = mul_i<1>(csub(cscale(ey, dkx), cscale(ex, dky)));
@@ -180,28 +181,28 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
             w[c][e] = rk_update<RKS>(nl[c], L, d, dt, idx, rs, B, R, pb);
           }
         } else {
-          const double a = dt * (dkx * dkx + dky * dky + kz * kz) / pb.Rm;
+          const Rl a = dt * (dkx * dkx + dky * dky + kz * kz) / (Rl)pb.Rm;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const int idx = (c * M + r) * M + kx + K;
-            const cplx b = PRE ? bo[c][PRE ? e : 0] : B[idx];
-            cplx bn;
+            const C b = PRE ? bo[c][PRE ? e : 0] : B[idx];
+            C bn;
             if (mode == 1) {
-              const double inv = 1.0 / (1.0 + a);
+              const Rl inv = (Rl)1 / ((Rl)1 + a);
               bn = cscale(cadd(b, cscale(nl[c], dt)), inv);
             } else {
-              const double inv = 1.0 / (1.5 + a);
-              const cplx h = PRE ? ho[c][PRE ? e : 0] : H[idx];
-              bn = cscale(cadd(cadd(cscale(b, 2.0), cscale(nl[c], 2.0 * dt)), h), inv);
+              const Rl inv = (Rl)1 / ((Rl)1.5 + a);
+              const C h = PRE ? ho[c][PRE ? e : 0] : H[idx];
+              bn = cscale(cadd(cadd(cscale(b, (Rl)2), cscale(nl[c], (Rl)2 * dt)), h), inv);
             }
-            H[idx] = csub(cscale(b, -0.5), cscale(nl[c], dt));
+            H[idx] = csub(cscale(b, (Rl)-0.5), cscale(nl[c], dt));
             B[idx] = bn;
             w[c][e] = bn;
           }
         }
       } else {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) w[c][e] = czero();
+        for (int c = 0; c < 3; ++c) w[c][e] = zero_of<C>();
       }
     }
   }
@@ -223,11 +224,12 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, cplx* s, cp
 // (pitch TX + 1) so that global loads and stores run along x and all three
 // are in flight at once; once every group holds its column in registers the
 // tile memory doubles as the groups' FFT exchange spans.
-template <int N, int E, int LANES, int CH>
-__device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restrict__ T1,
-                                         cplx* __restrict__ T2, const cplx* __restrict__ tw,
+template <int N, int E, int LANES, int CH, class C = cplx>
+__device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ T1,
+                                         C* __restrict__ T2, const C* __restrict__ tw,
                                          const FlowPhase& fp) {
   using G = Geo<N, E>;
+  using Rl = decltype(C::re);
   constexpr int T = G::T, K = G::K, M = G::M;
   constexpr int nthr = LANES;
   constexpr int TX = nthr / T < N ? nthr / T : N;
@@ -237,8 +239,8 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
   const int g = tid / T, j = tid % T;
   const int x = x0 + g;
   const bool active = g < TX && x < N;
-  cplx* s = tile + (g < TX ? g : 0) * G::SPAN;
-  TwRegs<N, E> twr;
+  C* s = tile + (g < TX ? g : 0) * G::SPAN;
+  TwRegs<N, E, C> twr;
   twr.load(j, tw);
   // each lane issues a chunk of CH tile loads before the chunk's LDS
   // stores, so the workgroup waits for global memory once a chunk, not once
@@ -246,13 +248,13 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
   constexpr int NIT = (3 * M * TX + nthr - 1) / nthr;
 #pragma unroll 1
   for (int i0 = 0; i0 < NIT; i0 += CH) {
-    cplx buf[CH];
+    C buf[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int i = tid + (i0 + q) * nthr;
       const int c = i / (M * TX), rem = i - c * (M * TX);
       const int r = rem / TX, cc = rem - r * TX;
-      buf[q] = (i0 + q < NIT && i < 3 * M * TX && x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : czero();
+      buf[q] = (i0 + q < NIT && i < 3 * M * TX && x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : zero_of<C>();
     }
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
@@ -263,13 +265,13 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
     }
   }
   __syncthreads();
-  cplx w[3][E];
+  C w[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = signed_k(j + T * e, N);
-      w[c][e] = (active && ky >= -K && ky <= K) ? tile[c * TS + (ky + K) * TP + g] : czero();
+      w[c][e] = (active && ky >= -K && ky <= K) ? tile[c * TS + (ky + K) * TP + g] : zero_of<C>();
     }
   __syncthreads();
   if (g < TX) {
@@ -277,17 +279,19 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
     for (int c = 0; c < 3; ++c) fft<N, E, 1>(w[c], s, j, twr);
     // E = u x b at (x, y_e)
     const int xa = active ? x : 0;
-    const double cx = tw[xa].re, sx = -tw[xa].im;
-    const double cxp = cx * fp.cpx - sx * fp.spx;   // cos(x + px)
-    const double sxp = sx * fp.cpx + cx * fp.spx;   // sin(x + px)
+    const Rl fcpx = (Rl)fp.cpx, fspx = (Rl)fp.spx, fcpy = (Rl)fp.cpy, fspy = (Rl)fp.spy;
+    const Rl famp = (Rl)fp.amp;
+    const Rl cx = tw[xa].re, sx = -tw[xa].im;
+    const Rl cxp = cx * fcpx - sx * fspx;   // cos(x + px)
+    const Rl sxp = sx * fcpx + cx * fspx;   // sin(x + px)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int m = j + T * e;
-      const double cy = tw[m].re, sy = -tw[m].im;
-      const double cyp = cy * fp.cpy - sy * fp.spy;  // cos(y + py)
-      const double syp = sy * fp.cpy + cy * fp.spy;  // sin(y + py)
-      const double ux = fp.amp * cyp, uy = fp.amp * sxp, uz = fp.amp * (cxp + syp);
-      const cplx bx = w[0][e], by = w[1][e], bz = w[2][e];
+      const Rl cy = tw[m].re, sy = -tw[m].im;
+      const Rl cyp = cy * fcpy - sy * fspy;  // cos(y + py)
+      const Rl syp = sy * fcpy + cy * fspy;  // sin(y + py)
+      const Rl ux = famp * cyp, uy = famp * sxp, uz = famp * (cxp + syp);
+      const C bx = w[0][e], by = w[1][e], bz = w[2][e];
       w[0][e] = csub(cscale(bz, uy), cscale(by, uz));
       w[1][e] = csub(cscale(bx, uz), cscale(bz, ux));
       w[2][e] = csub(cscale(by, ux), cscale(bx, uy));
@@ -308,13 +312,13 @@ __device__ __forceinline__ void col_tile(int x0, cplx* tile, const cplx* __restr
   __syncthreads();
 #pragma unroll 1
   for (int i0 = 0; i0 < NIT; i0 += CH) {
-    cplx buf[CH];
+    C buf[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int i = tid + (i0 + q) * nthr;
       const int c = i / (M * TX), rem = i - c * (M * TX);
       const int r = rem / TX, cc = rem - r * TX;
-      buf[q] = (i0 + q < NIT && i < 3 * M * TX) ? tile[c * TS + r * TP + cc] : czero();
+      buf[q] = (i0 + q < NIT && i < 3 * M * TX) ? tile[c * TS + r * TP + cc] : zero_of<C>();
     }
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
@@ -344,11 +348,11 @@ __host__ __device__ constexpr int tile_elems(int lanes) {
 
 // ---------------------------------------------------------------------------
 // Multi-launch path: one launch per phase over every (field, tile).
-template <int N, int E, int W, int RKS, bool PF = false>
-__global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int mode, int last) {
+template <int N, int E, int W, int RKS, bool PF = false, class C = cplx>
+__global__ __launch_bounds__(64 * W) void k_rows(FieldBatchT<C> fb, Problem pb, int mode, int last) {
   using G = Geo<N, E>;
   constexpr int RPW = W * 64 / G::T;
-  __shared__ cplx sm[RPW * G::SPAN];
+  __shared__ C sm[RPW * G::SPAN];
   if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
   const int g = threadIdx.x / G::T, j = threadIdx.x % G::T;
   const int r = blockIdx.x * RPW + g;
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(64 * W) void k_rows(FieldBatch fb, Problem pb, int 
   Problem p = pb;
   if (fb.fRm != nullptr) p.Rm = fb.fRm[f];
   if (fb.fkz != nullptr) p.kz = fb.fkz[f];
-  row_phase<N, E, RKS, PF>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
+  row_phase<N, E, RKS, PF, C>(r, r < G::M, j, sm + g * G::SPAN, fb.B + f * box, fb.H + f * box,
                        fb.T2 + f * rows, fb.T1 + f * rows, fb.tw, p, mode, last != 0,
                        RKS > 0 ? fb.R + 4 * f * box : nullptr);
 }
@@ -384,12 +388,12 @@ __device__ __forceinline__ void xcd_tile(int& tile, int& row) {
   row = L / nx;
 }
 
-template <int N, int E, int TX, int MINW>
+template <int N, int E, int TX, int MINW, class C = cplx>
 __global__ __launch_bounds__(TX * (N / E))
-__attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb, int step,
+__attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatchT<C> fb, Problem pb, int step,
                                                         int stage) {
   using G = Geo<N, E>;
-  __shared__ cplx tile[tile_elems<N, E>(TX * G::T)];
+  __shared__ C tile[tile_elems<N, E>(TX * G::T)];
   int xt, row;
   xcd_tile<TX>(xt, row);
   if (fb.count != nullptr && row >= *fb.count) return;
@@ -399,7 +403,7 @@ __attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatch fb, Problem pb
   const double t = stage == 0 ? fb.t0[f] + step * pb.dt
                               : fb.t0[f] + step * pb.dt + pb.rk_c[stage - 1] * pb.dt;
   const FlowPhase fp = flow_phase(pb, t);
-  col_tile<N, E, TX * G::T, E == 8 ? 8 : 4>(xt * TX, tile, fb.T1 + f * rows,
+  col_tile<N, E, TX * G::T, E == 8 ? 8 : 4, C>(xt * TX, tile, fb.T1 + f * rows,
                                             fb.T2 + f * rows, fb.tw, fp);
 }
 
@@ -676,9 +680,11 @@ __global__ __launch_bounds__(Shape<NC>::LANES) void k_sweep(SweepArgs a, Problem
 //   q = (0, +1): u_q = (A/2) e^{+i px} (0, -i, 1)
 //   q = (0, -1): u_q = (A/2) e^{-i px} (0, +i, 1)
 // The four coefficients alpha_+- = (A/2) e^{+-i py}, beta_+- = (A/2) e^{+-i px}.
-struct FlowModes {
-  cplx ap, am, bp, bm;
+template <class C = cplx>
+struct FlowModesT {
+  C ap, am, bp, bm;
 };
+using FlowModes = FlowModesT<cplx>;
 
 __device__ __forceinline__ FlowModes flow_modes(const Problem& pb, double t) {
   double px = 0.0, py = 0.0;
@@ -704,8 +710,8 @@ constexpr int CONV_MPL = (CONV_MMAX * CONV_MMAX + CONV_LANES - 1) / CONV_LANES; 
 
 // dt N = dt i k x E with (dkx, dky, dkz) = dt k: component c is
 // i (dk_{c+1} E_{c+2} - dk_{c+2} E_{c+1}).
-__device__ __forceinline__ void dt_curl(const cplx e[3], double dkx, double dky, double dkz,
-                                        cplx dn[3]) {
+template <class C, class Rl>
+__device__ __forceinline__ void dt_curl(const C e[3], Rl dkx, Rl dky, Rl dkz, C dn[3]) {
   dn[0] = mul_i<1>(csub(cscale(e[2], dky), cscale(e[1], dkz)));
   dn[1] = mul_i<1>(csub(cscale(e[0], dkz), cscale(e[2], dkx)));
   dn[2] = mul_i<1>(csub(cscale(e[1], dkx), cscale(e[0], dky)));
@@ -715,14 +721,15 @@ __device__ __forceinline__ void dt_curl(const cplx e[3], double dkx, double dky,
 // of one component from dN = dt N; h holds the previous step's -b/2 - dN on
 // entry and this step's on exit.  inv = 1 / (1 + dt|k|^2/Rm) or
 // 1 / (3/2 + dt|k|^2/Rm).
-__device__ __forceinline__ cplx sbdf_update(cplx b, cplx d, cplx& h, double inv, int step) {
-  cplx bn;
+template <class C, class Rl>
+__device__ __forceinline__ C sbdf_update(C b, C d, C& h, Rl inv, int step) {
+  C bn;
   if (step == 0) {
     bn = {(b.re + d.re) * inv, (b.im + d.im) * inv};
   } else {
-    bn = {(2.0 * b.re + (2.0 * d.re + h.re)) * inv, (2.0 * b.im + (2.0 * d.im + h.im)) * inv};
+    bn = {((Rl)2 * b.re + ((Rl)2 * d.re + h.re)) * inv, ((Rl)2 * b.im + ((Rl)2 * d.im + h.im)) * inv};
   }
-  h = {-0.5 * b.re - d.re, -0.5 * b.im - d.im};
+  h = {(Rl)-0.5 * b.re - d.re, (Rl)-0.5 * b.im - d.im};
   return bn;
 }
 
@@ -730,55 +737,60 @@ __device__ __forceinline__ cplx sbdf_update(cplx b, cplx d, cplx& h, double inv,
 // width, so the neighbours' offsets and the index arithmetic are constants);
 // lane l owns box modes l + CONV_LANES*m (state and history in registers)
 // and reads neighbours from LDS.
-template <int MC>
-__device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem& pb, int,
-                                               cplx* bs, double (*rs)[CONV_LANES]) {
+template <int MC, class C = cplx>
+__device__ __forceinline__ void sweep_conv_lds(const SweepArgsT<C>& a, const Problem& pb, int,
+                                               C* bs, double (*rs)[CONV_LANES]) {
+  using Rl = decltype(C::re);
   constexpr int Mc = MC;
   constexpr int Kc = (Mc - 1) / 2;
   constexpr int nbox = Mc * Mc;
   const int M = a.M, K = (a.M - 1) / 2;
   const size_t fbox = (size_t)3 * M * M;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double kz = pb.kz, dt = pb.dt, dkz = dt * kz;
+  const Rl kz = (Rl)pb.kz, dt = (Rl)pb.dt, dkz = dt * kz;
   // owned modes and their implicit factors (SBDF1, SBDF2)
   int own[CONV_MPL], oky[CONV_MPL], okx[CONV_MPL];
-  double inv1[CONV_MPL], inv2[CONV_MPL];
+  Rl inv1[CONV_MPL], inv2[CONV_MPL];
 #pragma unroll
   for (int m = 0; m < CONV_MPL; ++m) {
     own[m] = tid + m * nt;
     const int i = own[m] < nbox ? own[m] : 0;
     oky[m] = i / Mc - Kc;
     okx[m] = i % Mc - Kc;
-    const double kxd = okx[m], kyd = oky[m];
-    const double aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / pb.Rm;
-    inv1[m] = 1.0 / (1.0 + aa);
-    inv2[m] = 1.0 / (1.5 + aa);
+    const Rl kxd = okx[m], kyd = oky[m];
+    const Rl aa = dt * (kxd * kxd + kyd * kyd + kz * kz) / (Rl)pb.Rm;
+    inv1[m] = (Rl)1 / ((Rl)1 + aa);
+    inv2[m] = (Rl)1 / ((Rl)1.5 + aa);
   }
   for (int n = a.n0; n < a.P; ++n) {
-    const cplx* Un = a.U + n * fbox;
-    cplx h[CONV_MPL][3];
+    const C* Un = a.U + n * fbox;
+    C h[CONV_MPL][3];
 #pragma unroll
     for (int m = 0; m < CONV_MPL; ++m)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        h[m][c] = czero();
+        h[m][c] = zero_of<C>();
         if (own[m] < nbox) bs[c * nbox + own[m]] = Un[(c * M + oky[m] + K) * M + okx[m] + K];
       }
     __syncthreads();
     const double t0 = (a.nbase + n) * a.dT;
     for (int step = 0; step < a.nsteps; ++step) {
-      FlowModes fm;
+      FlowModesT<C> fm;
       if (a.ftab != nullptr && pb.tdep) {
         const double* ft = a.ftab + 4 * ((size_t)(a.nbase + n) * a.nsteps + step);
         const double h = 0.5 * pb.amp;
-        fm.ap = {h * ft[0], h * ft[1]};
-        fm.am = {h * ft[0], -h * ft[1]};
-        fm.bp = {h * ft[2], h * ft[3]};
-        fm.bm = {h * ft[2], -h * ft[3]};
+        fm.ap = {(Rl)(h * ft[0]), (Rl)(h * ft[1])};
+        fm.am = {(Rl)(h * ft[0]), (Rl)(-h * ft[1])};
+        fm.bp = {(Rl)(h * ft[2]), (Rl)(h * ft[3])};
+        fm.bm = {(Rl)(h * ft[2]), (Rl)(-h * ft[3])};
       } else {
-        fm = flow_modes(pb, t0 + step * dt);
+        const FlowModes fd = flow_modes(pb, t0 + step * pb.dt);
+        fm.ap = {(Rl)fd.ap.re, (Rl)fd.ap.im};
+        fm.am = {(Rl)fd.am.re, (Rl)fd.am.im};
+        fm.bp = {(Rl)fd.bp.re, (Rl)fd.bp.im};
+        fm.bm = {(Rl)fd.bm.re, (Rl)fd.bm.im};
       }
-      cplx bn[CONV_MPL][3];
+      C bn[CONV_MPL][3];
 #pragma unroll
       for (int m = 0; m < CONV_MPL; ++m) {
         if (own[m] >= nbox) continue;
@@ -789,43 +801,43 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
         //  q = (0,-1), u = bm (0, +i, 1): ( i bm bz - bm by,  bm bx, -i bm bx)
         // with the two-term entries taken as one product, e.g.
         // -i ap bx - ap bz = -ap (i bx + bz): two complex products a neighbour
-        cplx e[3] = {czero(), czero(), czero()};
+        C e[3] = {zero_of<C>(), zero_of<C>(), zero_of<C>()};
         const int ky = oky[m], kx = okx[m];
         if (ky - 1 >= -Kc) {
           const int si = (ky - 1 + Kc) * Mc + kx + Kc;
-          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
-          const cplx aby = cmul(fm.ap, by);
+          const C bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const C aby = cmul(fm.ap, by);
           e[0] = cadd(e[0], mul_i<1>(aby));
           e[1] = csub(e[1], cmul(fm.ap, cadd(mul_i<1>(bx), bz)));
           e[2] = cadd(e[2], aby);
         }
         if (ky + 1 <= Kc) {
           const int si = (ky + 1 + Kc) * Mc + kx + Kc;
-          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
-          const cplx aby = cmul(fm.am, by);
+          const C bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const C aby = cmul(fm.am, by);
           e[0] = csub(e[0], mul_i<1>(aby));
           e[1] = cadd(e[1], cmul(fm.am, csub(mul_i<1>(bx), bz)));
           e[2] = cadd(e[2], aby);
         }
         if (kx - 1 >= -Kc) {
           const int si = (ky + Kc) * Mc + kx - 1 + Kc;
-          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
-          const cplx bbx = cmul(fm.bp, bx);
+          const C bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const C bbx = cmul(fm.bp, bx);
           e[0] = csub(e[0], cmul(fm.bp, cadd(mul_i<1>(bz), by)));
           e[1] = cadd(e[1], bbx);
           e[2] = cadd(e[2], mul_i<1>(bbx));
         }
         if (kx + 1 <= Kc) {
           const int si = (ky + Kc) * Mc + kx + 1 + Kc;
-          const cplx bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
-          const cplx bbx = cmul(fm.bm, bx);
+          const C bx = bs[si], by = bs[nbox + si], bz = bs[2 * nbox + si];
+          const C bbx = cmul(fm.bm, bx);
           e[0] = cadd(e[0], cmul(fm.bm, csub(mul_i<1>(bz), by)));
           e[1] = cadd(e[1], bbx);
           e[2] = csub(e[2], mul_i<1>(bbx));
         }
-        cplx dn[3];
-        dt_curl(e, dt * kx, dt * ky, dkz, dn);
-        const double inv = step == 0 ? inv1[m] : inv2[m];
+        C dn[3];
+        dt_curl(e, dt * (Rl)kx, dt * (Rl)ky, dkz, dn);
+        const Rl inv = step == 0 ? inv1[m] : inv2[m];
 #pragma unroll
         for (int c = 0; c < 3; ++c) bn[m][c] = sbdf_update(bs[c * nbox + own[m]], dn[c], h[m][c], inv, step);
       }
@@ -838,13 +850,13 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
       __syncthreads();
     }
     // correction on the fine box: g = zero-padded coarse result
-    cplx* Un1 = a.U + (n + 1) * fbox;
-    cplx* Go = a.Gold + n * fbox;
-    const cplx* Fn = a.Fo + n * fbox;
+    C* Un1 = a.U + (n + 1) * fbox;
+    C* Go = a.Gold + n * fbox;
+    const C* Fn = a.Fo + n * fbox;
     for (int i = tid; i < (int)fbox; i += nt) {
       const int c = i / (M * M), r = (i / M) % M, cc = i % M;
       const int dr = r - K, dc = cc - K;
-      cplx g = czero();
+      C g = zero_of<C>();
       if (dr >= -Kc && dr <= Kc && dc >= -Kc && dc <= Kc) g = bs[c * nbox + (dr + Kc) * Mc + dc + Kc];
       if (a.mode == 0) {
         Un1[i] = g;
@@ -856,12 +868,13 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
     __syncthreads();
   }
   if (a.mode != 0 && a.red != nullptr) {
-    const cplx* UP = a.U + (size_t)a.P * fbox;
+    const C* UP = a.U + (size_t)a.P * fbox;
     double s0 = 0.0, s1 = 0.0;
     for (int i = tid; i < (int)fbox; i += nt) {
-      const cplx d = csub(UP[i], a.Uprev[i]);
-      s0 += d.re * d.re + d.im * d.im;
-      s1 += UP[i].re * UP[i].re + UP[i].im * UP[i].im;
+      const C d = csub(UP[i], a.Uprev[i]);
+      const double dr = d.re, di = d.im, ur = UP[i].re, ui = UP[i].im;
+      s0 += dr * dr + di * di;
+      s1 += ur * ur + ui * ui;
     }
     rs[0][tid] = s0;
     rs[1][tid] = s1;
@@ -881,11 +894,11 @@ __device__ __forceinline__ void sweep_conv_lds(const SweepArgs& a, const Problem
 }
 
 
-template <int MC>
-__global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgs a, Problem pb, int Mc) {
-  __shared__ cplx bs[3 * MC * MC];
+template <int MC, class C = cplx>
+__global__ __launch_bounds__(CONV_LANES) void k_sweep_conv(SweepArgsT<C> a, Problem pb, int Mc) {
+  __shared__ C bs[3 * MC * MC];
   __shared__ double rs[2][CONV_LANES];
-  sweep_conv_lds<MC>(a, pb, Mc, bs, rs);
+  sweep_conv_lds<MC, C>(a, pb, Mc, bs, rs);
 }
 
 // Defect sums |U_P - Uprev|^2, |U_P|^2 of one sweep, fixed-order tree.
@@ -1052,8 +1065,10 @@ __global__ __launch_bounds__(CONV_LANES) void k_sweep_conv_jobs(const SweepJob* 
 
 // ---------------------------------------------------------------------------
 // Layout conversion, box check, copies, norms.
-__global__ void k_pack(const cplx* __restrict__ full, cplx* __restrict__ box, int N, int M,
+template <class C>
+__global__ void k_pack(const cplx* __restrict__ full, C* __restrict__ box, int N, int M,
                        size_t nfields) {
+  using Rl = decltype(C::re);
   const int K = (M - 1) / 2;
   const size_t total = nfields * 3 * (size_t)M * M;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
@@ -1061,11 +1076,13 @@ __global__ void k_pack(const cplx* __restrict__ full, cplx* __restrict__ box, in
     const size_t fc = i / ((size_t)M * M);
     const int r = (int)((i / M) % M), c = (int)(i % M);
     const int ky = r - K, kx = c - K;
-    box[i] = full[fc * (size_t)N * N + (size_t)((ky + N) % N) * N + (kx + N) % N];
+    const cplx v = full[fc * (size_t)N * N + (size_t)((ky + N) % N) * N + (kx + N) % N];
+    box[i] = C{(Rl)v.re, (Rl)v.im};
   }
 }
 
-__global__ void k_unpack(const cplx* __restrict__ box, cplx* __restrict__ full, int N, int M,
+template <class C>
+__global__ void k_unpack(const C* __restrict__ box, cplx* __restrict__ full, int N, int M,
                          size_t nfields) {
   const int K = (M - 1) / 2;
   const size_t total = nfields * 3 * (size_t)N * N;
@@ -1075,8 +1092,10 @@ __global__ void k_unpack(const cplx* __restrict__ box, cplx* __restrict__ full, 
     const int my = (int)((i / N) % N), mx = (int)(i % N);
     const int ky = my < N / 2 ? my : my - N, kx = mx < N / 2 ? mx : mx - N;
     cplx v = czero();
-    if (ky >= -K && ky <= K && kx >= -K && kx <= K)
-      v = box[fc * (size_t)M * M + (size_t)(ky + K) * M + kx + K];
+    if (ky >= -K && ky <= K && kx >= -K && kx <= K) {
+      const C b = box[fc * (size_t)M * M + (size_t)(ky + K) * M + kx + K];
+      v = cplx{(double)b.re, (double)b.im};
+    }
     full[i] = v;
   }
 }
@@ -1113,8 +1132,9 @@ __global__ __launch_bounds__(256) void k_gather(const cplx* __restrict__ U, cplx
 // compact coarse box (its central block), and the Parareal update of one
 // slice from the coarse result (zero-padded prolongation):
 //   mode 0: U_{n+1} = g,  mode 1: U_{n+1} = F_n + (g - Gold_n);  Gold_n = g.
-__global__ __launch_bounds__(256) void k_box_restrict(const cplx* __restrict__ Un,
-                                                      cplx* __restrict__ Bc, int M, int Mc) {
+template <class C>
+__global__ __launch_bounds__(256) void k_box_restrict(const C* __restrict__ Un,
+                                                      C* __restrict__ Bc, int M, int Mc) {
   const int K = (M - 1) / 2, Kc = (Mc - 1) / 2;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < 3 * Mc * Mc; i += gridDim.x * 256) {
     const int c = i / (Mc * Mc), rr = (i / Mc) % Mc, cc = i % Mc;
@@ -1122,15 +1142,16 @@ __global__ __launch_bounds__(256) void k_box_restrict(const cplx* __restrict__ U
   }
 }
 
-__global__ __launch_bounds__(256) void k_box_correct(const cplx* __restrict__ Bc,
-                                                     const cplx* __restrict__ Fn,
-                                                     cplx* __restrict__ Go, cplx* __restrict__ Un1,
+template <class C>
+__global__ __launch_bounds__(256) void k_box_correct(const C* __restrict__ Bc,
+                                                     const C* __restrict__ Fn,
+                                                     C* __restrict__ Go, C* __restrict__ Un1,
                                                      int M, int Mc, int mode) {
   const int K = (M - 1) / 2, Kc = (Mc - 1) / 2;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < 3 * M * M; i += gridDim.x * 256) {
     const int c = i / (M * M), r = (i / M) % M, cc = i % M;
     const int dr = r - K, dc = cc - K;
-    cplx g = czero();
+    C g = zero_of<C>();
     if (dr >= -Kc && dr <= Kc && dc >= -Kc && dc <= Kc) g = Bc[(c * Mc + dr + Kc) * Mc + dc + Kc];
     Un1[i] = mode == 0 ? g : cadd(Fn[i], csub(g, Go[i]));
     Go[i] = g;
@@ -1138,12 +1159,16 @@ __global__ __launch_bounds__(256) void k_box_correct(const cplx* __restrict__ Bc
 }
 
 // per-field squared two-norm, fixed-order reduction (one workgroup a field)
-__global__ __launch_bounds__(256) void k_norm2(const cplx* __restrict__ x, size_t len,
+template <class C>
+__global__ __launch_bounds__(256) void k_norm2(const C* __restrict__ x, size_t len,
                                                double* out) {
   __shared__ double rs[256];
-  const cplx* p = x + blockIdx.x * len;
+  const C* p = x + blockIdx.x * len;
   double s = 0.0;
-  for (size_t i = threadIdx.x; i < len; i += 256) s += p[i].re * p[i].re + p[i].im * p[i].im;
+  for (size_t i = threadIdx.x; i < len; i += 256) {
+    const double re = p[i].re, im = p[i].im;
+    s += re * re + im * im;
+  }
   rs[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -1581,12 +1606,12 @@ hipError_t sweep_multi(int Nc, const SweepArgs& a, const Problem& pb, hipStream_
   fb.tw = a.twc;
   fb.R = a.Rc;
   for (int n = a.n0; n < a.P; ++n) {
-    hipLaunchKernelGGL(k_box_restrict, dim3(gb < 1024 ? gb : 1024), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_box_restrict<cplx>, dim3(gb < 1024 ? gb : 1024), dim3(256), 0, st,
                        a.U + n * fbox, a.Bc, a.M, Mc);
     fb.t0 = a.t0s + n;
     hipError_t e = propagate(Nc, fb, pb, 1, a.nsteps, PATH_MULTI, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_box_correct, dim3(gf < 1024 ? gf : 1024), dim3(256), 0, st, a.Bc,
+    hipLaunchKernelGGL(k_box_correct<cplx>, dim3(gf < 1024 ? gf : 1024), dim3(256), 0, st, a.Bc,
                        a.Fo + n * fbox, a.Gold + n * fbox, a.U + (n + 1) * fbox, a.M, Mc, a.mode);
   }
   return hipGetLastError();
@@ -1599,13 +1624,13 @@ static int grid_for(size_t total) {
 }
 
 hipError_t pack(const cplx* full, cplx* box, int N, int M, size_t nfields, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack, dim3(grid_for(nfields * 3 * (size_t)M * M)), dim3(256), 0, st, full,
+  hipLaunchKernelGGL(k_pack<cplx>, dim3(grid_for(nfields * 3 * (size_t)M * M)), dim3(256), 0, st, full,
                      box, N, M, nfields);
   return hipGetLastError();
 }
 
 hipError_t unpack(const cplx* box, cplx* full, int N, int M, size_t nfields, hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack, dim3(grid_for(nfields * 3 * (size_t)N * N)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_unpack<cplx>, dim3(grid_for(nfields * 3 * (size_t)N * N)), dim3(256), 0, st,
                      box, full, N, M, nfields);
   return hipGetLastError();
 }
@@ -1625,7 +1650,170 @@ hipError_t gather(const cplx* U, cplx* Fo, const int* uidx, const int* map, cons
 }
 
 hipError_t norms2(const cplx* x, size_t len, int nfields, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_norm2, dim3(nfields), dim3(256), 0, st, x, len, out);
+  hipLaunchKernelGGL(k_norm2<cplx>, dim3(nfields), dim3(256), 0, st, x, len, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The complex64 variant: the same kernels on FP32 values (SBDF2 fine and
+// coarse steps, the multi-launch path), one launch shape per grid size.
+template <int N>
+struct ShapeF {
+  static constexpr int RE = 8, RW = 1;  // rows: values a lane, waves a workgroup
+  static constexpr int CE = N >= 128 ? 8 : 4;
+  static constexpr int CTX = N >= 256 ? 8 : (N == 128 ? 16 : (N == 64 ? 32 : 16));
+};
+
+template <int N>
+static hipError_t launch_rows_f(const FieldBatchF& fb, const Problem& pb, int nfields, int mode,
+                                int last, hipStream_t st) {
+  constexpr int E = ShapeF<N>::RE, W = ShapeF<N>::RW;
+  using G = Geo<N, E>;
+  constexpr int RPW = W * 64 / G::T;
+  if (mode >= ROW_RK) return hipErrorInvalidValue;  // SBDF2 only
+  dim3 grid((G::M + RPW - 1) / RPW, nfields);
+  hipLaunchKernelGGL((k_rows<N, E, W, 0, false, cplxf>), grid, dim3(64 * W), 0, st, fb, pb, mode,
+                     last);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_cols_f(const FieldBatchF& fb, const Problem& pb, int nfields, int step,
+                                hipStream_t st) {
+  constexpr int E = ShapeF<N>::CE, TX = ShapeF<N>::CTX, T = N / E;
+  dim3 grid((N + TX - 1) / TX, nfields);
+  hipLaunchKernelGGL((k_cols<N, E, TX, 4, cplxf>), grid, dim3(TX * T), 0, st, fb, pb, step, 0);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t propagate_f(const FieldBatchF& fb, const Problem& pb, int nfields, int nsteps,
+                              hipStream_t st) {
+  hipError_t e = launch_rows_f<N>(fb, pb, nfields, 0, 0, st);
+  for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+    e = launch_cols_f<N>(fb, pb, nfields, s, st);
+    if (e == hipSuccess) e = launch_rows_f<N>(fb, pb, nfields, s == 0 ? 1 : 2, s == nsteps - 1, st);
+  }
+  return e;
+}
+
+#define PD_SIZE_SWITCH(CALL)          \
+  switch (N) {                        \
+    case 16: return CALL(16);         \
+    case 32: return CALL(32);         \
+    case 64: return CALL(64);         \
+    case 128: return CALL(128);       \
+    case 256: return CALL(256);       \
+    case 512: return CALL(512);       \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t propagate(int N, const FieldBatchF& fb, const Problem& pb, int nfields, int nsteps,
+                     int, hipStream_t st) {
+  if (nfields <= 0 || nsteps <= 0) return hipSuccess;
+  if (pb.scheme != 0) return hipErrorInvalidValue;
+#define CALL(n) propagate_f<n>(fb, pb, nfields, nsteps, st)
+  PD_SIZE_SWITCH(CALL)
+#undef CALL
+}
+
+hipError_t rows(int N, const FieldBatchF& fb, const Problem& pb, int nfields, int mode, int last,
+                hipStream_t st) {
+#define CALL(n) launch_rows_f<n>(fb, pb, nfields, mode, last, st)
+  PD_SIZE_SWITCH(CALL)
+#undef CALL
+}
+
+hipError_t cols(int N, const FieldBatchF& fb, const Problem& pb, int nfields, int step,
+                hipStream_t st) {
+#define CALL(n) launch_cols_f<n>(fb, pb, nfields, step, st)
+  PD_SIZE_SWITCH(CALL)
+#undef CALL
+}
+#undef PD_SIZE_SWITCH
+
+hipError_t sweep_conv(int Nc, const SweepArgsF& a, const Problem& pb, hipStream_t st) {
+  const int Mc = 2 * ((Nc - 1) / 3) + 1;
+  if (!conv_lds_width(Mc) || pb.scheme != 0) return hipErrorInvalidValue;
+  switch (Mc) {
+    case 11: hipLaunchKernelGGL((k_sweep_conv<11, cplxf>), dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc); break;
+    case 21: hipLaunchKernelGGL((k_sweep_conv<21, cplxf>), dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc); break;
+    case 43: hipLaunchKernelGGL((k_sweep_conv<43, cplxf>), dim3(1), dim3(CONV_LANES), 0, st, a, pb, Mc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t sweep_multi(int Nc, const SweepArgsF& a, const Problem& pb, hipStream_t st) {
+  if (pb.scheme != 0 || a.t0s == nullptr) return hipErrorInvalidValue;
+  const int Mc = 2 * ((Nc - 1) / 3) + 1;
+  const size_t fbox = (size_t)3 * a.M * a.M;
+  const int gb = (int)((3 * Mc * Mc + 255) / 256), gf = (int)((fbox + 255) / 256);
+  FieldBatchF fb;
+  fb.B = a.Bc;
+  fb.H = a.Hc;
+  fb.T1 = a.T1c;
+  fb.T2 = a.T2c;
+  fb.tw = a.twc;
+  for (int n = a.n0; n < a.P; ++n) {
+    hipLaunchKernelGGL(k_box_restrict<cplxf>, dim3(gb < 1024 ? gb : 1024), dim3(256), 0, st,
+                       a.U + n * fbox, a.Bc, a.M, Mc);
+    fb.t0 = a.t0s + n;
+    hipError_t e = propagate(Nc, fb, pb, 1, a.nsteps, PATH_MULTI, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_box_correct<cplxf>, dim3(gf < 1024 ? gf : 1024), dim3(256), 0, st, a.Bc,
+                       a.Fo + n * fbox, a.Gold + n * fbox, a.U + (n + 1) * fbox, a.M, Mc, a.mode);
+  }
+  return hipGetLastError();
+}
+
+hipError_t pack(const cplx* full, cplxf* box, int N, int M, size_t nfields, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack<cplxf>, dim3(grid_for(nfields * 3 * (size_t)M * M)), dim3(256), 0, st,
+                     full, box, N, M, nfields);
+  return hipGetLastError();
+}
+
+hipError_t unpack(const cplxf* box, cplx* full, int N, int M, size_t nfields, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack<cplxf>, dim3(grid_for(nfields * 3 * (size_t)N * N)), dim3(256), 0,
+                     st, box, full, N, M, nfields);
+  return hipGetLastError();
+}
+
+hipError_t norms2(const cplxf* x, size_t len, int nfields, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2<cplxf>, dim3(nfields), dim3(256), 0, st, x, len, out);
+  return hipGetLastError();
+}
+
+// red[0] = |u - v|^2, red[1] = |u|^2, one workgroup, fixed order (FP64 sums)
+__global__ __launch_bounds__(256) void k_defect_f(const cplxf* __restrict__ u,
+                                                  const cplxf* __restrict__ v, size_t n,
+                                                  double* __restrict__ red) {
+  __shared__ double rs[2][256];
+  double s0 = 0.0, s1 = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += 256) {
+    const double dr = (double)u[i].re - (double)v[i].re, di = (double)u[i].im - (double)v[i].im;
+    const double ur = u[i].re, ui = u[i].im;
+    s0 += dr * dr + di * di;
+    s1 += ur * ur + ui * ui;
+  }
+  rs[0][threadIdx.x] = s0;
+  rs[1][threadIdx.x] = s1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      rs[0][threadIdx.x] += rs[0][threadIdx.x + w];
+      rs[1][threadIdx.x] += rs[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    red[0] = rs[0][0];
+    red[1] = rs[1][0];
+  }
+}
+
+hipError_t defect2(const cplxf* u, const cplxf* v, size_t n, double* red, hipStream_t st) {
+  hipLaunchKernelGGL(k_defect_f, dim3(1), dim3(256), 0, st, u, v, n, red);
   return hipGetLastError();
 }
 

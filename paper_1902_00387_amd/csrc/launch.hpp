@@ -32,15 +32,17 @@ struct Problem {
   double rk_at[5][4] = {};
 };
 
-// A batch of fields stepped together (all of grid size N).
-struct FieldBatch {
-  cplx* B = nullptr;           // [f][3][M][M] state (in: start value, out: end value)
-  cplx* H = nullptr;           // [f][3][M][M] SBDF2 history workspace
-  cplx* T1 = nullptr;          // [f][3][M][N] row workspace
-  cplx* T2 = nullptr;          // [f][3][M][N] row workspace
+// A batch of fields stepped together (all of grid size N), complex128 (C =
+// cplx) or complex64 (C = cplxf).
+template <class C>
+struct FieldBatchT {
+  C* B = nullptr;              // [f][3][M][M] state (in: start value, out: end value)
+  C* H = nullptr;              // [f][3][M][M] SBDF2 history workspace
+  C* T1 = nullptr;             // [f][3][M][N] row workspace
+  C* T2 = nullptr;             // [f][3][M][N] row workspace
   const double* t0 = nullptr;  // [f] start time of each field's slice
-  const cplx* tw = nullptr;    // [N] twiddles e^{-2 pi i m/N}
-  cplx* R = nullptr;           // [f][4][3][M][M] Runge-Kutta stage sums (scheme 1 only)
+  const C* tw = nullptr;       // [N] twiddles e^{-2 pi i m/N}
+  C* R = nullptr;              // [f][4][3][M][M] Runge-Kutta stage sums (scheme 1 only)
   // optional (null: use the Problem's scalars / the identity map)
   const double* fRm = nullptr;  // [f] per-field Rm
   const double* fkz = nullptr;  // [f] per-field kz
@@ -48,20 +50,20 @@ struct FieldBatch {
   const int* count = nullptr;   // device count of active launch rows
   int rows_v = -1, cols_v = -1;  // launch-shape variants for this batch (-1: process-wide choice)
 };
+using FieldBatch = FieldBatchT<cplx>;
+using FieldBatchF = FieldBatchT<cplxf>;
 
-struct SweepArgs;
-// One instance's coarse sweep in a batched sweep launch.
-struct SweepJob;
-
-struct SweepArgs {
-  cplx* U = nullptr;            // [P+1][3][M][M] slice-boundary states (fine, compact)
-  const cplx* Fo = nullptr;     // [P][3][M][M] fine results F(U^{k-1}_n)
-  cplx* Gold = nullptr;         // [P][3][M][M] previous coarse results
-  const cplx* Uprev = nullptr;  // [3][M][M] U^{k-1}_P (defect; the batched sweep fills it)
-  cplx *Bc = nullptr, *Hc = nullptr, *T1c = nullptr, *T2c = nullptr;  // coarse workspaces
-  cplx* Rc = nullptr;           // [4][3][Mc][Mc] coarse Runge-Kutta stage sums (scheme 1)
+// One serial coarse sweep (complex128, or complex64 with C = cplxf).
+template <class C>
+struct SweepArgsT {
+  C* U = nullptr;               // [P+1][3][M][M] slice-boundary states (fine, compact)
+  const C* Fo = nullptr;        // [P][3][M][M] fine results F(U^{k-1}_n)
+  C* Gold = nullptr;            // [P][3][M][M] previous coarse results
+  const C* Uprev = nullptr;     // [3][M][M] U^{k-1}_P (defect; the batched sweep fills it)
+  C *Bc = nullptr, *Hc = nullptr, *T1c = nullptr, *T2c = nullptr;  // coarse workspaces
+  C* Rc = nullptr;              // [4][3][Mc][Mc] coarse Runge-Kutta stage sums (scheme 1)
   const double* t0s = nullptr;  // [P] slice start times (multi-launch sweep only)
-  const cplx* twc = nullptr;    // coarse twiddles
+  const C* twc = nullptr;       // coarse twiddles
   double* red = nullptr;        // [2] defect sums (may be null)
   const double* ftab = nullptr; // [P][nsteps][4] cos(py), sin(py), cos(px), sin(px) of the
                       // flow phases at every coarse step time (time-dependent flow)
@@ -72,6 +74,8 @@ struct SweepArgs {
   int mode;           // 0: initial coarse run, 1: correction
   int nbase = 0;      // absolute index of local slice 0 (start time (nbase + n) dT)
 };
+using SweepArgs = SweepArgsT<cplx>;
+using SweepArgsF = SweepArgsT<cplxf>;
 
 struct SweepJob {
   SweepArgs a;
@@ -82,6 +86,20 @@ struct SweepJob {
 
 hipError_t propagate(int N, const FieldBatch& fb, const Problem& pb, int nfields, int nsteps,
                      int path, hipStream_t st);
+// the complex64 variant: FP32 kernels, SBDF2, the default launch shapes
+hipError_t propagate(int N, const FieldBatchF& fb, const Problem& pb, int nfields, int nsteps,
+                     int path, hipStream_t st);
+hipError_t rows(int N, const FieldBatchF& fb, const Problem& pb, int nfields, int mode, int last,
+                hipStream_t st);
+hipError_t cols(int N, const FieldBatchF& fb, const Problem& pb, int nfields, int step,
+                hipStream_t st);
+hipError_t sweep_conv(int Nc, const SweepArgsF& a, const Problem& pb, hipStream_t st);
+hipError_t sweep_multi(int Nc, const SweepArgsF& a, const Problem& pb, hipStream_t st);
+hipError_t pack(const cplx* full, cplxf* box, int N, int M, size_t nfields, hipStream_t st);
+hipError_t unpack(const cplxf* box, cplx* full, int N, int M, size_t nfields, hipStream_t st);
+hipError_t norms2(const cplxf* x, size_t len, int nfields, double* out, hipStream_t st);
+// red[0] = |u - v|^2, red[1] = |u|^2 (one workgroup, fixed order)
+hipError_t defect2(const cplxf* u, const cplxf* v, size_t n, double* red, hipStream_t st);
 // single launches of the two phases of the multi-launch path
 hipError_t rows(int N, const FieldBatch& fb, const Problem& pb, int nfields, int mode, int last,
                 hipStream_t st);

@@ -199,6 +199,7 @@ pd_status pd_lg_init(pd_ctx* c, int layers, uint64_t seed) {
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (layers < 1 || layers > 8) return fail(c, PD_EINVAL, "layers must be in [1, 8]");
+  if (c->prec == PD_C64) return fail(c, PD_EINVAL, "the learned coarse propagator is complex128 only");
   DeviceGuard dg(c->device);
   lg_release(c);
   auto& g = c->lg;

@@ -49,8 +49,10 @@ pd_status ensure_pipeline_streams(pd_ctx* c) {
 }
 
 // Same contract as pd_parareal (plain coarse propagator only); kres >= 0
-// resumes after iteration kres with U and Gold already loaded.
-pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep) {
+// resumes after iteration kres with U and Gold already loaded.  CT: the
+// context's complex type (complex128 or complex64).
+template <class CT>
+static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep) {
   const auto wall0 = std::chrono::steady_clock::now();
   pd_status s = ensure_pipeline_streams(c);
   if (s != PD_OK) return s;
@@ -60,8 +62,8 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   const int C = (P + Sc - 1) / Sc;  // chunks of Sc slices, the last one nonempty
   auto lo = [&](int ch) { return std::min(P, ch * Sc); };
   auto hi = [&](int ch) { return std::min(P, (ch + 1) * Sc); };
-  cplx* U = c->U.as<cplx>();
-  cplx* Fo = c->Fo.as<cplx>();
+  CT* U = c->U.as<CT>();
+  CT* Fo = c->Fo.as<CT>();
   // two fine streams, the context's own and one more: a chunk's fine launches
   // are latency-bound, so chunks run side by side to keep the chip as busy as
   // one full sweep.  HIP spreads a process's streams over a few hardware
@@ -85,17 +87,17 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   hipEvent_t evIn = E.ev[10 * C], evRed = E.ev[10 * C + 1];
   hipEvent_t evJoin[2] = {E.ev[10 * C + 2], E.ev[10 * C + 3]};
 
-  pd::SweepArgs sa;
+  pd::SweepArgsT<CT> sa;
   sa.U = U;
   sa.Fo = Fo;
-  sa.Gold = c->Gold.as<cplx>();
-  sa.Uprev = c->Uprev.as<cplx>();
-  sa.Bc = c->Bc.as<cplx>();
-  sa.Hc = c->Hc.as<cplx>();
-  sa.T1c = c->T1c.as<cplx>();
-  sa.T2c = c->T2c.as<cplx>();
-  sa.twc = c->twc.as<cplx>();
-  sa.Rc = c->Rc.as<cplx>();
+  sa.Gold = c->Gold.as<CT>();
+  sa.Uprev = c->Uprev.as<CT>();
+  sa.Bc = c->Bc.as<CT>();
+  sa.Hc = c->Hc.as<CT>();
+  sa.T1c = c->T1c.as<CT>();
+  sa.T2c = c->T2c.as<CT>();
+  sa.twc = c->twidc<CT>();
+  sa.Rc = c->Rc.as<CT>();
   sa.ftab = c->ftab.as<double>();
   sa.dT = c->dT;
   sa.M = c->M;
@@ -138,19 +140,20 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
       const int a = std::max(lo(ch), n0), b = hi(ch);
       if (a < b)
         PD_HIP(c, hipMemcpyAsync(Fo + (size_t)a * box, U + (size_t)a * box,
-                                 (size_t)(b - a) * box * sizeof(cplx), hipMemcpyDeviceToDevice, st),
+                                 (size_t)(b - a) * box * sizeof(CT), hipMemcpyDeviceToDevice, st),
                "copy");
       PD_HIP(c, hipEventRecord(Fc(k, ch), st), "event");
       if (a < b) {
-        pd::FieldBatch fb;
+        pd::FieldBatchT<CT> fb;
         fb.B = Fo + (size_t)a * box;
-        fb.H = c->Hf.as<cplx>() + (size_t)a * box;
-        fb.T1 = c->T1f.as<cplx>() + (size_t)a * rows;
-        fb.T2 = c->T2f.as<cplx>() + (size_t)a * rows;
+        fb.H = c->Hf.as<CT>() + (size_t)a * box;
+        fb.T1 = c->T1f.as<CT>() + (size_t)a * rows;
+        fb.T2 = c->T2f.as<CT>() + (size_t)a * rows;
         fb.t0 = c->t0s.as<double>() + a;
-        fb.tw = c->tw.as<cplx>();
+        fb.tw = c->twid<CT>();
         c->shapes(fb);
-        if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * a * box;
+        if constexpr (sizeof(CT) == sizeof(cplx))
+          if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * a * box;
         int path = choose_path(c, b - a);
         if (path == PD_PATH_MULTI2) path = PD_PATH_MULTI;  // the chunks already use two streams
         PD_HIP(c, pd::propagate(c->N, fb, pf, b - a, c->nf, path, st), "fine sweep");
@@ -174,7 +177,7 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
     s = enqueue_fine(k, fine_done, C);
     if (s != PD_OK) return s;
     // coarse sweep of iteration k with the correction, chunk by chunk
-    PD_HIP(c, hipMemcpyAsync(c->Uprev.p, U + (size_t)P * box, box * sizeof(cplx),
+    PD_HIP(c, hipMemcpyAsync(c->Uprev.p, U + (size_t)P * box, box * sizeof(CT),
                              hipMemcpyDeviceToDevice, cs), "copy");
     for (int ch = 0; ch < C; ++ch) {
       // this chunk's fine results, and the next chunk's start value U^{k-1}
@@ -244,6 +247,11 @@ pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   finish_report(r, P);
   if (rep) *rep = r;
   return status;
+}
+
+pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep) {
+  return c->prec == PD_C64 ? pipelined_t<cplxf>(c, tol, max_iter, kres, rep)
+                           : pipelined_t<cplx>(c, tol, max_iter, kres, rep);
 }
 
 }  // namespace ctxh

@@ -149,6 +149,34 @@ hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb
   return pd::propagate(c->N, fb, pb, nfields, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st);
 }
 
+// complex64: the convolution sweep (N_C <= 64) or the multi-launch sweep
+// followed by the defect sums
+hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgsF& sa, const pd::Problem& pc, hipStream_t st) {
+  if (use_conv_sweep(c)) return pd::sweep_conv(c->Nc, sa, pc, st);
+  if (sa.t0s == nullptr) sa.t0s = c->t0s.as<double>() + sa.nbase;
+  hipError_t e = pd::sweep_multi(c->Nc, sa, pc, st);
+  if (e == hipSuccess && sa.mode != 0 && sa.red != nullptr)
+    e = pd::defect2(sa.U + (size_t)sa.P * c->box_elems(), sa.Uprev, c->box_elems(), sa.red, st);
+  return e;
+}
+
+hipError_t fine_batch(pd_ctx* c, const pd::FieldBatchF& fb, const pd::Problem& pb, int nfields,
+                      int nsteps, hipStream_t st) {
+  return pd::propagate(c->N, fb, pb, nfields, nsteps, pd::PATH_MULTI, st);
+}
+
+pd_status upload_twiddles(pd_ctx* c, int N, DevBuf& d64, DevBuf& d32, hipStream_t st) {
+  const std::vector<cplx> tw = twiddles(N);
+  std::vector<cplxf> twf(N);
+  for (int m = 0; m < N; ++m) twf[m] = {(float)tw[m].re, (float)tw[m].im};
+  PD_HIP(c, d64.ensure(sizeof(cplx) * N), "alloc twiddles");
+  PD_HIP(c, d32.ensure(sizeof(cplxf) * N), "alloc twiddles");
+  PD_HIP(c, hipMemcpyAsync(d64.p, tw.data(), sizeof(cplx) * N, hipMemcpyHostToDevice, st), "copy");
+  PD_HIP(c, hipMemcpyAsync(d32.p, twf.data(), sizeof(cplxf) * N, hipMemcpyHostToDevice, st), "copy");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  return PD_OK;
+}
+
 // Validate `nfields` full-layout device fields: zero outside the 2/3 box.
 pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStream_t st) {
   PD_HIP(c, c->flag.ensure(sizeof(int)), "alloc");
@@ -163,7 +191,61 @@ pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStre
 }
 
 // Propagate `batch` full-layout fields by nsteps steps of dt on grid N (with
-// restriction to Ngrid <= N and zero-padding back when Ngrid < N).
+// restriction to Ngrid <= N and zero-padding back when Ngrid < N), in the
+// context's number type C.
+template <class C>
+static pd_status run_propagator_t(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
+                                  int Ngrid, const void* d_in, void* d_out, hipStream_t st,
+                                  int scheme) {
+  pd_status s = check_box_dev(c, d_in, c->N, batch, st);
+  if (s != PD_OK) return s;
+  const int Mg = box_M(Ngrid);
+  const size_t box = (size_t)3 * Mg * Mg, rows = (size_t)3 * Mg * Ngrid;
+  PD_HIP(c, c->wB.ensure(box * batch * sizeof(C)), "alloc");
+  PD_HIP(c, c->wH.ensure(box * batch * sizeof(C)), "alloc");
+  PD_HIP(c, c->wT1.ensure(rows * batch * sizeof(C)), "alloc");
+  PD_HIP(c, c->wT2.ensure(rows * batch * sizeof(C)), "alloc");
+  PD_HIP(c, c->wt0.ensure(sizeof(double) * batch), "alloc");
+  PD_HIP(c, hipMemcpyAsync(c->wt0.p, t0, sizeof(double) * batch, hipMemcpyHostToDevice, st),
+         "copy t0");
+  const C* twg = c->twid<C>();
+  if (Ngrid != c->N) {
+    s = upload_twiddles(c, Ngrid, c->twc, c->twcf, st);
+    if (s != PD_OK) return s;
+    twg = c->twidc<C>();
+  }
+  // full layout on N -> compact box of Ngrid: for Ngrid < N the pack keeps
+  // only |k| <= Kg (restriction) and the unpack zero-pads (prolongation)
+  PD_HIP(c, pd::pack(static_cast<const cplx*>(d_in), c->wB.as<C>(), c->N, Mg, (size_t)batch, st),
+         "pack");
+  pd::FieldBatchT<C> fb;
+  fb.B = c->wB.as<C>();
+  fb.H = c->wH.as<C>();
+  fb.T1 = c->wT1.as<C>();
+  fb.T2 = c->wT2.as<C>();
+  fb.t0 = c->wt0.as<double>();
+  fb.tw = twg;
+  if constexpr (sizeof(C) == sizeof(cplx)) {
+    if (scheme != PD_SCHEME_SBDF2) {
+      PD_HIP(c, c->wR.ensure(4 * box * batch * sizeof(cplx)), "alloc");
+      fb.R = c->wR.as<cplx>();
+    }
+  }
+  const pd::Problem pb = make_problem(c, dt, scheme);
+  if (Ngrid == c->N) {
+    c->shapes(fb);
+    PD_HIP(c, fine_batch(c, fb, pb, batch, nsteps, st), "propagate");
+  } else {
+    const int path = choose_path(c, batch);
+    PD_HIP(c, pd::propagate(Ngrid, fb, pb, batch, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st),
+           "propagate");
+  }
+  PD_HIP(c, pd::unpack(c->wB.as<C>(), static_cast<cplx*>(d_out), c->N, Mg, (size_t)batch, st),
+         "unpack");
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  return PD_OK;
+}
+
 pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int nsteps,
                          int Ngrid, const void* d_in, void* d_out, hipStream_t st, int scheme) {
   if (!c->have_problem) return fail(c, PD_ESTATE, "pd_set_problem not called");
@@ -175,60 +257,256 @@ pd_status run_propagator(pd_ctx* c, const double* t0, int batch, double dt, int 
   for (int f = 0; f < batch; ++f)
     if (!std::isfinite(t0[f])) return fail(c, PD_EINVAL, "t0 must be finite");
   DeviceGuard dg(c->device);
-  pd_status s = check_box_dev(c, d_in, c->N, batch, st);
-  if (s != PD_OK) return s;
-  const int Mg = box_M(Ngrid);
-  const size_t box = (size_t)3 * Mg * Mg, rows = (size_t)3 * Mg * Ngrid;
-  PD_HIP(c, c->wB.ensure(box * batch * sizeof(cplx)), "alloc");
-  PD_HIP(c, c->wH.ensure(box * batch * sizeof(cplx)), "alloc");
-  PD_HIP(c, c->wT1.ensure(rows * batch * sizeof(cplx)), "alloc");
-  PD_HIP(c, c->wT2.ensure(rows * batch * sizeof(cplx)), "alloc");
-  PD_HIP(c, c->wt0.ensure(sizeof(double) * batch), "alloc");
-  PD_HIP(c, hipMemcpyAsync(c->wt0.p, t0, sizeof(double) * batch, hipMemcpyHostToDevice, st),
-         "copy t0");
-  DevBuf* twb = &c->tw;
-  if (Ngrid != c->N) {
-    std::vector<cplx> tw = twiddles(Ngrid);
-    PD_HIP(c, c->twc.ensure(sizeof(cplx) * Ngrid), "alloc");
-    PD_HIP(c, hipMemcpyAsync(c->twc.p, tw.data(), sizeof(cplx) * Ngrid, hipMemcpyHostToDevice, st),
-           "copy tw");
-    PD_HIP(c, hipStreamSynchronize(st), "sync");
-    twb = &c->twc;
+  if (c->prec == PD_C64) {
+    if (scheme != PD_SCHEME_SBDF2) return fail(c, PD_EINVAL, "complex64 steps SBDF2 only");
+    return run_propagator_t<cplxf>(c, t0, batch, dt, nsteps, Ngrid, d_in, d_out, st, scheme);
   }
-  // full layout on N -> compact box of Ngrid: for Ngrid < N the pack keeps
-  // only |k| <= Kg (restriction) and the unpack zero-pads (prolongation)
-  PD_HIP(c, pd::pack(static_cast<const cplx*>(d_in), c->wB.as<cplx>(), c->N, Mg, (size_t)batch, st),
-         "pack");
-  pd::FieldBatch fb;
-  fb.B = c->wB.as<cplx>();
-  fb.H = c->wH.as<cplx>();
-  fb.T1 = c->wT1.as<cplx>();
-  fb.T2 = c->wT2.as<cplx>();
-  fb.t0 = c->wt0.as<double>();
-  fb.tw = twb->as<cplx>();
-  if (scheme != PD_SCHEME_SBDF2) {
-    PD_HIP(c, c->wR.ensure(4 * box * batch * sizeof(cplx)), "alloc");
-    fb.R = c->wR.as<cplx>();
-  }
-  const pd::Problem pb = make_problem(c, dt, scheme);
-  if (Ngrid == c->N) {
-    c->shapes(fb);
-    PD_HIP(c, fine_batch(c, fb, pb, batch, nsteps, st), "propagate");
-  } else {
-    const int path = choose_path(c, batch);
-    PD_HIP(c, pd::propagate(Ngrid, fb, pb, batch, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st),
-           "propagate");
-  }
-  PD_HIP(c, pd::unpack(c->wB.as<cplx>(), static_cast<cplx*>(d_out), c->N, Mg, (size_t)batch, st),
-         "unpack");
-  PD_HIP(c, hipStreamSynchronize(st), "sync");
-  return PD_OK;
+  return run_propagator_t<cplx>(c, t0, batch, dt, nsteps, Ngrid, d_in, d_out, st, scheme);
 }
 
 }  // namespace ctxh
 }  // namespace pd
 
 using namespace pd::ctxh;
+
+// The plain order of Parareal (Section 3): every fine sweep, then the serial
+// coarse sweep with the correction and the defect, on the context's stream,
+// in the context's number type C (the learned coarse propagator: complex128).
+template <class C>
+static pd_status parareal_plain(pd_ctx* c, double tol, int max_iter, int kres, bool learned,
+                                pd_report* rep, std::chrono::steady_clock::time_point wall0) {
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems(), rows = c->rows_elems();
+  const int P = c->P;
+  C* U = c->U.as<C>();
+  C* Fo = c->Fo.as<C>();
+  pd_report r;
+  std::memset(&r, 0, sizeof r);
+  r.k_con = -1;
+  hipEvent_t ev[4];
+  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); }
+  } evf{ev};
+
+  pd::SweepArgsT<C> sa;
+  sa.U = U;
+  sa.Fo = Fo;
+  sa.Gold = c->Gold.as<C>();
+  sa.Uprev = c->Uprev.as<C>();
+  sa.Bc = c->Bc.as<C>();
+  sa.Hc = c->Hc.as<C>();
+  sa.T1c = c->T1c.as<C>();
+  sa.T2c = c->T2c.as<C>();
+  sa.twc = c->twidc<C>();
+  sa.Rc = c->Rc.as<C>();
+  sa.red = c->red.as<double>();
+  sa.ftab = c->ftab.as<double>();
+  sa.dT = c->dT;
+  sa.M = c->M;
+  sa.P = P;
+  sa.nsteps = c->nc;
+  const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
+                    pf = make_problem(c, c->dtf, c->scheme_f);
+
+  // initial coarse run (Section 3: U^0_n from G over [0, T])
+  sa.n0 = 0;
+  sa.mode = 0;
+  PD_HIP(c, hipEventRecord(ev[0], st), "event");
+  auto run_sweep = [&]() -> hipError_t {
+    return coarse_sweep(c, sa, pc, st);
+  };
+  if (kres >= 0) {
+    // nothing to do: the state of iteration kres was supplied
+  } else if (learned) {
+    if constexpr (sizeof(C) == sizeof(cplx)) {
+      pd_status ls = lg_sweep(c, 0, true, st);
+      if (ls != PD_OK) return ls;
+    }
+  } else {
+    PD_HIP(c, run_sweep(), "coarse sweep");
+  }
+  PD_HIP(c, hipEventRecord(ev[1], st), "event");
+  PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+  float ms = 0;
+  PD_HIP(c, hipEventElapsedTime(&ms, ev[0], ev[1]), "event");
+  r.t_coarse0_s = ms * 1e-3;
+
+  pd_status status = PD_NOT_CONVERGED;
+  for (int k = kres >= 0 ? kres + 1 : 1; k <= max_iter; ++k) {
+    const int n0 = k - 1 < P - 1 ? k - 1 : P - 1;
+    PD_HIP(c, hipMemcpyAsync(c->Uprev.p, U + (size_t)P * box, box * sizeof(C),
+                             hipMemcpyDeviceToDevice, st), "copy");
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    // fine sweep over the slices whose start value can still change
+    PD_HIP(c, hipMemcpyAsync(Fo + (size_t)n0 * box, U + (size_t)n0 * box,
+                             (size_t)(P - n0) * box * sizeof(C), hipMemcpyDeviceToDevice, st),
+           "copy");
+    pd::FieldBatchT<C> fb;
+    fb.B = Fo + (size_t)n0 * box;
+    fb.H = c->Hf.as<C>() + (size_t)n0 * box;
+    fb.T1 = c->T1f.as<C>() + (size_t)n0 * rows;
+    fb.T2 = c->T2f.as<C>() + (size_t)n0 * rows;
+    fb.t0 = c->t0s.as<double>() + n0;
+    fb.tw = c->twid<C>();
+    c->shapes(fb);
+    if constexpr (sizeof(C) == sizeof(cplx))
+      if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
+    PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
+    PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    // serial coarse sweep with the correction, then the defect sums
+    sa.n0 = n0;
+    sa.mode = 1;
+    if (learned) {
+      if constexpr (sizeof(C) == sizeof(cplx)) {
+        pd_status ls = lg_sweep(c, n0, false, st);
+        if (ls != PD_OK) return ls;
+      }
+    } else {
+      PD_HIP(c, run_sweep(), "coarse sweep");
+    }
+    PD_HIP(c, hipEventRecord(ev[2], st), "event");
+    PD_HIP(c, hipMemcpyAsync(c->hred, c->red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    PD_HIP(c, hipStreamSynchronize(st), "sync");
+    float mf = 0, mc = 0;
+    PD_HIP(c, hipEventElapsedTime(&mf, ev[0], ev[1]), "event");
+    PD_HIP(c, hipEventElapsedTime(&mc, ev[1], ev[2]), "event");
+    r.t_fine_s += mf * 1e-3;
+    r.t_coarse_s += mc * 1e-3;
+    const double num = c->hred[0], den = c->hred[1];
+    r.iters = k;
+    if (!std::isfinite(num) || !std::isfinite(den)) {
+      status = fail(c, PD_EUNSTABLE, "non-finite state at iteration %d (unstable step size?)", k);
+      break;
+    }
+    const double sigma = den > 0 ? std::sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+    r.sigma[k - 1] = sigma;
+    if (sigma <= tol) {
+      r.k_con = k;
+      status = PD_OK;
+      break;
+    }
+  }
+  if (max_iter == 0) status = PD_OK;
+  r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+  finish_report(r, c->P);
+  if (rep) *rep = r;
+  return status;
+}
+
+
+template <class C>
+static pd_status profile_fine_t(pd_ctx* c, int reps, double* ms) {
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems();
+  const int P = c->P;
+  hipEvent_t ev[2];
+  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } evf{ev};
+  auto fresh = [&]() -> hipError_t {
+    return hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(C), hipMemcpyDeviceToDevice, st);
+  };
+  pd::FieldBatchT<C> fb;
+  fb.B = c->Fo.as<C>();
+  fb.H = c->Hf.as<C>();
+  fb.T1 = c->T1f.as<C>();
+  fb.T2 = c->T2f.as<C>();
+  fb.t0 = c->t0s.as<double>();
+  fb.tw = c->twid<C>();
+  c->shapes(fb);
+  const pd::Problem pf = make_problem(c, c->dtf);
+  float t = 0;
+  // a whole fine sweep (all slices, every step) as Parareal launches it
+  PD_HIP(c, fresh(), "copy");
+  PD_HIP(c, hipEventRecord(ev[0], st), "event");
+  PD_HIP(c, fine_batch(c, fb, pf, P, c->nf, st), "propagate");
+  PD_HIP(c, hipEventRecord(ev[1], st), "event");
+  PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+  PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+  ms[2] = t / c->nf;
+  ms[0] = ms[1] = 0.0;
+  if (choose_path(c, P) != pd::PATH_SINGLE_WG) {
+    // each phase kernel back to back, reps times, over the same batch
+    PD_HIP(c, fresh(), "copy");
+    PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    for (int i = 0; i < reps; ++i) PD_HIP(c, pd::cols(c->N, fb, pf, P, 1, st), "cols");
+    PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+    PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+    ms[0] = t / reps;
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    for (int i = 0; i < reps; ++i) PD_HIP(c, pd::rows(c->N, fb, pf, P, 2, 0, st), "rows");
+    PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+    PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+    ms[1] = t / reps;
+  }
+  return PD_OK;
+}
+
+
+template <class C>
+static pd_status fine_sweep_steps_t(pd_ctx* c, int step0, int n_steps, double* ms) {
+  hipStream_t st = c->stream;
+  const size_t box = c->box_elems();
+  const int P = c->P;
+  pd::FieldBatchT<C> fb;
+  fb.B = c->Fo.as<C>();
+  fb.H = c->Hf.as<C>();
+  fb.T1 = c->T1f.as<C>();
+  fb.T2 = c->T2f.as<C>();
+  fb.t0 = c->t0s.as<double>();
+  fb.tw = c->twid<C>();
+  c->shapes(fb);
+  const pd::Problem pf = make_problem(c, c->dtf);
+  c->sweep_next = -1;
+  if (step0 == 0) {
+    PD_HIP(c, hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(C),
+                             hipMemcpyDeviceToDevice, st), "copy");
+    PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
+  }
+  std::vector<hipEvent_t> ev;
+  struct EvFree {
+    std::vector<hipEvent_t>& e;
+    ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }
+  } evf{ev};
+  if (ms) {
+    ev.resize((size_t)2 * n_steps + 1, nullptr);
+    for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+    PD_HIP(c, hipEventRecord(ev[0], st), "event");
+  }
+  for (int s = step0; s < step0 + n_steps; ++s) {
+    const int i = s - step0;
+    PD_HIP(c, pd::cols(c->N, fb, pf, P, s, st), "cols");
+    if (ms) PD_HIP(c, hipEventRecord(ev[2 * i + 1], st), "event");
+    PD_HIP(c, pd::rows(c->N, fb, pf, P, s == 0 ? 1 : 2, 0, st), "rows");
+    if (ms) PD_HIP(c, hipEventRecord(ev[2 * i + 2], st), "event");
+  }
+  PD_HIP(c, hipStreamSynchronize(st), "sync");
+  if (ms) {
+    double tc = 0.0, tr = 0.0;
+    for (int i = 0; i < n_steps; ++i) {
+      float a = 0.f, b = 0.f;
+      PD_HIP(c, hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]), "event");
+      PD_HIP(c, hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]), "event");
+      tc += a;
+      tr += b;
+    }
+    float all = 0.f;
+    PD_HIP(c, hipEventElapsedTime(&all, ev[0], ev[2 * n_steps]), "event");
+    ms[0] = tc;
+    ms[1] = tr;
+    ms[2] = all;
+  }
+  c->sweep_next = step0 + n_steps;
+  return PD_OK;
+}
+
 
 extern "C" {
 
@@ -279,7 +557,8 @@ void pd_destroy(pd_ctx* c) {
       if (e) (void)hipEventDestroy(e);
     if (c->hred) (void)hipHostFree(c->hred);
     lg_release(c);
-    c->tw.release(); c->twc.release(); c->U.release(); c->Fo.release(); c->Gold.release();
+    c->tw.release(); c->twc.release(); c->twf.release(); c->twcf.release();
+    c->U.release(); c->Fo.release(); c->Gold.release();
     c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
     c->Bc.release(); c->Hc.release(); c->T1c.release(); c->T2c.release(); c->red.release();
     c->ftab.release(); c->Rf.release(); c->Rc.release(); c->wR.release();
@@ -321,6 +600,8 @@ pd_status pd_set_scheme(pd_ctx* c, pd_scheme fine, pd_scheme coarse) {
     if (v < PD_SCHEME_SBDF2 || v > PD_SCHEME_RK111) return fail(c, PD_EINVAL, "unknown scheme %d", v);
   if (coarse != PD_SCHEME_SBDF2 && c->coarse_form == PD_COARSE_CONV)
     return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
+  if (c->prec == PD_C64 && (fine != PD_SCHEME_SBDF2 || coarse != PD_SCHEME_SBDF2))
+    return fail(c, PD_EINVAL, "complex64 steps SBDF2 only");
   c->scheme_f = fine;
   c->scheme_c = coarse;
   DeviceGuard dg(c->device);
@@ -335,7 +616,30 @@ pd_status pd_set_coarse_form(pd_ctx* c, pd_coarse_form f) {
     return fail(c, PD_EINVAL, "the convolution form of the coarse sweep steps SBDF2 only");
   if (f == PD_COARSE_CONV && c->have_time && c->Nc > 64)
     return fail(c, PD_EINVAL, "the convolution coarse sweep needs N_coarse <= 64");
+  if (f == PD_COARSE_FFT && c->prec == PD_C64)
+    return fail(c, PD_EINVAL, "complex64 has no one-workgroup FFT coarse sweep");
   c->coarse_form = f;
+  return PD_OK;
+}
+
+pd_status pd_set_precision(pd_ctx* c, pd_prec prec) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (prec != PD_C128 && prec != PD_C64) return fail(c, PD_EINVAL, "unknown precision %d", (int)prec);
+  if (prec == PD_C64 && (c->scheme_f != PD_SCHEME_SBDF2 || c->scheme_c != PD_SCHEME_SBDF2))
+    return fail(c, PD_EINVAL, "complex64 steps SBDF2 only");
+  if (prec == PD_C64 && c->coarse_form == PD_COARSE_FFT)
+    return fail(c, PD_EINVAL, "complex64 has no one-workgroup FFT coarse sweep");
+  if (prec == c->prec) return PD_OK;
+  DeviceGuard dg(c->device);
+  c->sweep_next = -1;
+  c->have_time = c->have_initial = false;
+  c->resume_k = -1;
+  lg_release(c);
+  c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
+  c->T2f.release(); c->Uprev.release(); c->Bc.release(); c->Hc.release(); c->T1c.release();
+  c->T2c.release();
+  c->prec = prec;
   return PD_OK;
 }
 
@@ -361,9 +665,10 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   c->N = N;
   c->K = box_K(N);
   c->M = box_M(N);
-  std::vector<cplx> tw = twiddles(N);
-  PD_HIP(c, c->tw.ensure(sizeof(cplx) * N), "alloc twiddles");
-  PD_HIP(c, hipMemcpy(c->tw.p, tw.data(), sizeof(cplx) * N, hipMemcpyHostToDevice), "copy");
+  {
+    pd_status ts = upload_twiddles(c, N, c->tw, c->twf, c->stream);
+    if (ts != PD_OK) return ts;
+  }
   c->have_problem = true;
   return PD_OK;
 }
@@ -387,8 +692,13 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   lg_release(c);
   c->T = T; c->P = P; c->dT = dT; c->dtf = dtf; c->dtc = dtc; c->Nc = Nc; c->Mc = box_M(Nc);
   c->nf = nf; c->nc = nc;
-  const size_t box = c->box_elems() * sizeof(cplx), rows = c->rows_elems() * sizeof(cplx);
-  const size_t cbox = (size_t)3 * c->Mc * c->Mc * sizeof(cplx), crows = (size_t)3 * c->Mc * Nc * sizeof(cplx);
+  if (c->prec == PD_C64 && (c->scheme_f != PD_SCHEME_SBDF2 || c->scheme_c != PD_SCHEME_SBDF2))
+    return fail(c, PD_EINVAL, "complex64 steps SBDF2 only");
+  if (c->prec == PD_C64 && c->coarse_form == PD_COARSE_FFT)
+    return fail(c, PD_EINVAL, "complex64 has no one-workgroup FFT coarse sweep");
+  const size_t es = c->esize();
+  const size_t box = c->box_elems() * es, rows = c->rows_elems() * es;
+  const size_t cbox = (size_t)3 * c->Mc * c->Mc * es, crows = (size_t)3 * c->Mc * Nc * es;
   PD_HIP(c, c->U.ensure(box * (P + 1)), "alloc U");
   PD_HIP(c, c->Fo.ensure(box * P), "alloc F");
   PD_HIP(c, c->Gold.ensure(box * P), "alloc Gold");
@@ -405,9 +715,10 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   std::vector<double> t0(P);
   for (int n = 0; n < P; ++n) t0[n] = n * dT;
   PD_HIP(c, hipMemcpy(c->t0s.p, t0.data(), sizeof(double) * P, hipMemcpyHostToDevice), "copy");
-  std::vector<cplx> twc = twiddles(Nc);
-  PD_HIP(c, c->twc.ensure(sizeof(cplx) * Nc), "alloc");
-  PD_HIP(c, hipMemcpy(c->twc.p, twc.data(), sizeof(cplx) * Nc, hipMemcpyHostToDevice), "copy");
+  {
+    pd_status ts = upload_twiddles(c, Nc, c->twc, c->twcf, c->stream);
+    if (ts != PD_OK) return ts;
+  }
   PD_HIP(c, hipMemset(c->U.p, 0, box * (P + 1)), "memset");
   // phases of the time-dependent flow at the coarse step times t = n dT + j dt_c:
   // (cos py, sin py, cos px, sin px) with px = cos t, py = sin t
@@ -440,7 +751,10 @@ pd_status pd_set_initial_dev(pd_ctx* c, const void* d_b0, void* s) {
   hipStream_t st = static_cast<hipStream_t>(s);
   pd_status r = check_box_dev(c, d_b0, c->N, 1, st);
   if (r != PD_OK) return r;
-  PD_HIP(c, pd::pack(static_cast<const cplx*>(d_b0), c->U.as<cplx>(), c->N, c->M, 1, st), "pack");
+  if (c->prec == PD_C64)
+    PD_HIP(c, pd::pack(static_cast<const cplx*>(d_b0), c->U.as<cplxf>(), c->N, c->M, 1, st), "pack");
+  else
+    PD_HIP(c, pd::pack(static_cast<const cplx*>(d_b0), c->U.as<cplx>(), c->N, c->M, 1, st), "pack");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   c->have_initial = true;
   c->resume_k = -1;
@@ -466,7 +780,10 @@ pd_status pd_set_initial(pd_ctx* c, const double* b0) {
   const size_t bytes = (size_t)3 * N * N * sizeof(cplx);
   PD_HIP(c, tmp.ensure(bytes), "alloc");
   PD_HIP(c, hipMemcpyAsync(tmp.p, b0, bytes, hipMemcpyHostToDevice, c->stream), "copy");
-  PD_HIP(c, pd::pack(tmp.as<cplx>(), c->U.as<cplx>(), N, c->M, 1, c->stream), "pack");
+  if (c->prec == PD_C64)
+    PD_HIP(c, pd::pack(tmp.as<cplx>(), c->U.as<cplxf>(), N, c->M, 1, c->stream), "pack");
+  else
+    PD_HIP(c, pd::pack(tmp.as<cplx>(), c->U.as<cplx>(), N, c->M, 1, c->stream), "pack");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
   c->have_initial = true;
   c->resume_k = -1;
@@ -508,11 +825,6 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   if (!(tol >= 0)) return fail(c, PD_EINVAL, "tol must be >= 0");
   DeviceGuard dg(c->device);
   const auto wall0 = std::chrono::steady_clock::now();
-  hipStream_t st = c->stream;
-  const size_t box = c->box_elems(), rows = c->rows_elems();
-  const int P = c->P;
-  cplx* U = c->U.as<cplx>();
-  cplx* Fo = c->Fo.as<cplx>();
   // resumed run (pd_set_slices): U holds U^k, Gold holds G(U^k_n)
   const int kres = c->resume_k;
   const bool learned = c->lg.enabled && c->lg.init;
@@ -526,114 +838,8 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     if (rs != PD_OK) return rs;
   }
   if (!learned && c->pipe_chunks > 1) return parareal_pipelined(c, tol, max_iter, kres, rep);
-  pd_report r;
-  std::memset(&r, 0, sizeof r);
-  r.k_con = -1;
-  hipEvent_t ev[4];
-  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
-  struct EvFree {
-    hipEvent_t* e;
-    ~EvFree() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); }
-  } evf{ev};
-
-  pd::SweepArgs sa;
-  sa.U = U;
-  sa.Fo = Fo;
-  sa.Gold = c->Gold.as<cplx>();
-  sa.Uprev = c->Uprev.as<cplx>();
-  sa.Bc = c->Bc.as<cplx>();
-  sa.Hc = c->Hc.as<cplx>();
-  sa.T1c = c->T1c.as<cplx>();
-  sa.T2c = c->T2c.as<cplx>();
-  sa.twc = c->twc.as<cplx>();
-  sa.Rc = c->Rc.as<cplx>();
-  sa.red = c->red.as<double>();
-  sa.ftab = c->ftab.as<double>();
-  sa.dT = c->dT;
-  sa.M = c->M;
-  sa.P = P;
-  sa.nsteps = c->nc;
-  const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
-                    pf = make_problem(c, c->dtf, c->scheme_f);
-
-  // initial coarse run (Section 3: U^0_n from G over [0, T])
-  sa.n0 = 0;
-  sa.mode = 0;
-  PD_HIP(c, hipEventRecord(ev[0], st), "event");
-  auto run_sweep = [&]() -> hipError_t {
-    return coarse_sweep(c, sa, pc, st);
-  };
-  if (kres >= 0) {
-    // nothing to do: the state of iteration kres was supplied
-  } else if (learned) {
-    pd_status ls = lg_sweep(c, 0, true, st);
-    if (ls != PD_OK) return ls;
-  } else {
-    PD_HIP(c, run_sweep(), "coarse sweep");
-  }
-  PD_HIP(c, hipEventRecord(ev[1], st), "event");
-  PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
-  float ms = 0;
-  PD_HIP(c, hipEventElapsedTime(&ms, ev[0], ev[1]), "event");
-  r.t_coarse0_s = ms * 1e-3;
-
-  pd_status status = PD_NOT_CONVERGED;
-  for (int k = kres >= 0 ? kres + 1 : 1; k <= max_iter; ++k) {
-    const int n0 = k - 1 < P - 1 ? k - 1 : P - 1;
-    PD_HIP(c, hipMemcpyAsync(c->Uprev.p, U + (size_t)P * box, box * sizeof(cplx),
-                             hipMemcpyDeviceToDevice, st), "copy");
-    PD_HIP(c, hipEventRecord(ev[0], st), "event");
-    // fine sweep over the slices whose start value can still change
-    PD_HIP(c, hipMemcpyAsync(Fo + (size_t)n0 * box, U + (size_t)n0 * box,
-                             (size_t)(P - n0) * box * sizeof(cplx), hipMemcpyDeviceToDevice, st),
-           "copy");
-    pd::FieldBatch fb;
-    fb.B = Fo + (size_t)n0 * box;
-    fb.H = c->Hf.as<cplx>() + (size_t)n0 * box;
-    fb.T1 = c->T1f.as<cplx>() + (size_t)n0 * rows;
-    fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
-    fb.t0 = c->t0s.as<double>() + n0;
-    fb.tw = c->tw.as<cplx>();
-    c->shapes(fb);
-    if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * n0 * box;
-    PD_HIP(c, fine_batch(c, fb, pf, P - n0, c->nf, st), "fine sweep");
-    PD_HIP(c, hipEventRecord(ev[1], st), "event");
-    // serial coarse sweep with the correction, then the defect sums
-    sa.n0 = n0;
-    sa.mode = 1;
-    if (learned) {
-      pd_status ls = lg_sweep(c, n0, false, st);
-      if (ls != PD_OK) return ls;
-    } else {
-      PD_HIP(c, run_sweep(), "coarse sweep");
-    }
-    PD_HIP(c, hipEventRecord(ev[2], st), "event");
-    PD_HIP(c, hipMemcpyAsync(c->hred, c->red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
-    PD_HIP(c, hipStreamSynchronize(st), "sync");
-    float mf = 0, mc = 0;
-    PD_HIP(c, hipEventElapsedTime(&mf, ev[0], ev[1]), "event");
-    PD_HIP(c, hipEventElapsedTime(&mc, ev[1], ev[2]), "event");
-    r.t_fine_s += mf * 1e-3;
-    r.t_coarse_s += mc * 1e-3;
-    const double num = c->hred[0], den = c->hred[1];
-    r.iters = k;
-    if (!std::isfinite(num) || !std::isfinite(den)) {
-      status = fail(c, PD_EUNSTABLE, "non-finite state at iteration %d (unstable step size?)", k);
-      break;
-    }
-    const double sigma = den > 0 ? std::sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
-    r.sigma[k - 1] = sigma;
-    if (sigma <= tol) {
-      r.k_con = k;
-      status = PD_OK;
-      break;
-    }
-  }
-  if (max_iter == 0) status = PD_OK;
-  r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
-  finish_report(r, c->P);
-  if (rep) *rep = r;
-  return status;
+  if (c->prec == PD_C64) return parareal_plain<cplxf>(c, tol, max_iter, kres, false, rep, wall0);
+  return parareal_plain<cplx>(c, tol, max_iter, kres, learned, rep, wall0);
 }
 
 pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
@@ -643,55 +849,7 @@ pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (reps < 1 || !ms) return fail(c, PD_EINVAL, "reps must be >= 1 and ms non-null");
   DeviceGuard dg(c->device);
-  hipStream_t st = c->stream;
-  const size_t box = c->box_elems();
-  const int P = c->P;
-  hipEvent_t ev[2];
-  for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
-  struct EvFree {
-    hipEvent_t* e;
-    ~EvFree() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
-  } evf{ev};
-  auto fresh = [&]() -> hipError_t {
-    return hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx), hipMemcpyDeviceToDevice, st);
-  };
-  pd::FieldBatch fb;
-  fb.B = c->Fo.as<cplx>();
-  fb.H = c->Hf.as<cplx>();
-  fb.T1 = c->T1f.as<cplx>();
-  fb.T2 = c->T2f.as<cplx>();
-  fb.t0 = c->t0s.as<double>();
-  fb.tw = c->tw.as<cplx>();
-  c->shapes(fb);
-  const pd::Problem pf = make_problem(c, c->dtf);
-  float t = 0;
-  // a whole fine sweep (all slices, every step) as Parareal launches it
-  PD_HIP(c, fresh(), "copy");
-  PD_HIP(c, hipEventRecord(ev[0], st), "event");
-  PD_HIP(c, fine_batch(c, fb, pf, P, c->nf, st), "propagate");
-  PD_HIP(c, hipEventRecord(ev[1], st), "event");
-  PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
-  PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
-  ms[2] = t / c->nf;
-  ms[0] = ms[1] = 0.0;
-  if (choose_path(c, P) != pd::PATH_SINGLE_WG) {
-    // each phase kernel back to back, reps times, over the same batch
-    PD_HIP(c, fresh(), "copy");
-    PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
-    PD_HIP(c, hipEventRecord(ev[0], st), "event");
-    for (int i = 0; i < reps; ++i) PD_HIP(c, pd::cols(c->N, fb, pf, P, 1, st), "cols");
-    PD_HIP(c, hipEventRecord(ev[1], st), "event");
-    PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
-    PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
-    ms[0] = t / reps;
-    PD_HIP(c, hipEventRecord(ev[0], st), "event");
-    for (int i = 0; i < reps; ++i) PD_HIP(c, pd::rows(c->N, fb, pf, P, 2, 0, st), "rows");
-    PD_HIP(c, hipEventRecord(ev[1], st), "event");
-    PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
-    PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
-    ms[1] = t / reps;
-  }
-  return PD_OK;
+  return c->prec == PD_C64 ? profile_fine_t<cplxf>(c, reps, ms) : profile_fine_t<cplx>(c, reps, ms);
 }
 
 pd_status pd_fine_sweep_steps(pd_ctx* c, int step0, int n_steps, double* ms) {
@@ -705,59 +863,8 @@ pd_status pd_fine_sweep_steps(pd_ctx* c, int step0, int n_steps, double* ms) {
   if (step0 > 0 && c->sweep_next != step0)
     return fail(c, PD_ESTATE, "the fine sweep stands at step %d, not %d", c->sweep_next, step0);
   DeviceGuard dg(c->device);
-  hipStream_t st = c->stream;
-  const size_t box = c->box_elems();
-  const int P = c->P;
-  pd::FieldBatch fb;
-  fb.B = c->Fo.as<cplx>();
-  fb.H = c->Hf.as<cplx>();
-  fb.T1 = c->T1f.as<cplx>();
-  fb.T2 = c->T2f.as<cplx>();
-  fb.t0 = c->t0s.as<double>();
-  fb.tw = c->tw.as<cplx>();
-  c->shapes(fb);
-  const pd::Problem pf = make_problem(c, c->dtf);
-  c->sweep_next = -1;
-  if (step0 == 0) {
-    PD_HIP(c, hipMemcpyAsync(c->Fo.p, c->U.p, (size_t)P * box * sizeof(cplx),
-                             hipMemcpyDeviceToDevice, st), "copy");
-    PD_HIP(c, pd::rows(c->N, fb, pf, P, 0, 0, st), "rows");
-  }
-  std::vector<hipEvent_t> ev;
-  struct EvFree {
-    std::vector<hipEvent_t>& e;
-    ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }
-  } evf{ev};
-  if (ms) {
-    ev.resize((size_t)2 * n_steps + 1, nullptr);
-    for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
-    PD_HIP(c, hipEventRecord(ev[0], st), "event");
-  }
-  for (int s = step0; s < step0 + n_steps; ++s) {
-    const int i = s - step0;
-    PD_HIP(c, pd::cols(c->N, fb, pf, P, s, st), "cols");
-    if (ms) PD_HIP(c, hipEventRecord(ev[2 * i + 1], st), "event");
-    PD_HIP(c, pd::rows(c->N, fb, pf, P, s == 0 ? 1 : 2, 0, st), "rows");
-    if (ms) PD_HIP(c, hipEventRecord(ev[2 * i + 2], st), "event");
-  }
-  PD_HIP(c, hipStreamSynchronize(st), "sync");
-  if (ms) {
-    double tc = 0.0, tr = 0.0;
-    for (int i = 0; i < n_steps; ++i) {
-      float a = 0.f, b = 0.f;
-      PD_HIP(c, hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]), "event");
-      PD_HIP(c, hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]), "event");
-      tc += a;
-      tr += b;
-    }
-    float all = 0.f;
-    PD_HIP(c, hipEventElapsedTime(&all, ev[0], ev[2 * n_steps]), "event");
-    ms[0] = tc;
-    ms[1] = tr;
-    ms[2] = all;
-  }
-  c->sweep_next = step0 + n_steps;
-  return PD_OK;
+  return c->prec == PD_C64 ? fine_sweep_steps_t<cplxf>(c, step0, n_steps, ms)
+                           : fine_sweep_steps_t<cplx>(c, step0, n_steps, ms);
 }
 
 // ---- autotuner --------------------------------------------------------------
@@ -844,6 +951,7 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   c->err.clear();
   if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
   if (reps < 1) return fail(c, PD_EINVAL, "reps must be >= 1");
+  if (c->prec == PD_C64) return fail(c, PD_EINVAL, "complex64 has one launch shape per grid");
   DeviceGuard dg(c->device);
   const int P = c->P;
   const std::string key = tune_key(c->device, c->N, P);
@@ -941,7 +1049,10 @@ pd_status pd_get_slices_dev(const pd_ctx* cc, void* d_out, void* s) {
   if (!d_out) return fail(c, PD_EINVAL, "null pointer argument");
   DeviceGuard dg(c->device);
   hipStream_t st = static_cast<hipStream_t>(s);
-  PD_HIP(c, pd::unpack(c->U.as<cplx>(), static_cast<cplx*>(d_out), c->N, c->M, (size_t)c->P + 1, st), "unpack");
+  if (c->prec == PD_C64)
+    PD_HIP(c, pd::unpack(c->U.as<cplxf>(), static_cast<cplx*>(d_out), c->N, c->M, (size_t)c->P + 1, st), "unpack");
+  else
+    PD_HIP(c, pd::unpack(c->U.as<cplx>(), static_cast<cplx*>(d_out), c->N, c->M, (size_t)c->P + 1, st), "unpack");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   return PD_OK;
 }
@@ -957,8 +1068,12 @@ pd_status pd_get_fine_states_dev(const pd_ctx* cc, int first, int count, void* d
   if (!d_out) return fail(c, PD_EINVAL, "null pointer argument");
   DeviceGuard dg(c->device);
   hipStream_t st = static_cast<hipStream_t>(s);
-  PD_HIP(c, pd::unpack(c->Fo.as<cplx>() + (size_t)first * c->box_elems(), static_cast<cplx*>(d_out),
-                       c->N, c->M, (size_t)count, st), "unpack");
+  if (c->prec == PD_C64)
+    PD_HIP(c, pd::unpack(c->Fo.as<cplxf>() + (size_t)first * c->box_elems(), static_cast<cplx*>(d_out),
+                         c->N, c->M, (size_t)count, st), "unpack");
+  else
+    PD_HIP(c, pd::unpack(c->Fo.as<cplx>() + (size_t)first * c->box_elems(), static_cast<cplx*>(d_out),
+                         c->N, c->M, (size_t)count, st), "unpack");
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   return PD_OK;
 }
@@ -974,7 +1089,10 @@ pd_status pd_get_slices(const pd_ctx* cc, double* out) {
   DevBuf tmp;
   PD_HIP(c, tmp.ensure(full * sizeof(cplx)), "alloc");
   for (int n = 0; n <= c->P; ++n) {
-    PD_HIP(c, pd::unpack(c->U.as<cplx>() + (size_t)n * c->box_elems(), tmp.as<cplx>(), c->N, c->M, 1, c->stream), "unpack");
+    if (c->prec == PD_C64)
+      PD_HIP(c, pd::unpack(c->U.as<cplxf>() + (size_t)n * c->box_elems(), tmp.as<cplx>(), c->N, c->M, 1, c->stream), "unpack");
+    else
+      PD_HIP(c, pd::unpack(c->U.as<cplx>() + (size_t)n * c->box_elems(), tmp.as<cplx>(), c->N, c->M, 1, c->stream), "unpack");
     PD_HIP(c, hipMemcpyAsync(out + 2 * full * n, tmp.p, full * sizeof(cplx), hipMemcpyDeviceToHost, c->stream), "copy");
   }
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
@@ -990,7 +1108,10 @@ pd_status pd_slice_norms(const pd_ctx* cc, double* norms) {
   DeviceGuard dg(c->device);
   DevBuf d;
   PD_HIP(c, d.ensure(sizeof(double) * (c->P + 1)), "alloc");
-  PD_HIP(c, pd::norms2(c->U.as<cplx>(), c->box_elems(), c->P + 1, d.as<double>(), c->stream), "norms");
+  if (c->prec == PD_C64)
+    PD_HIP(c, pd::norms2(c->U.as<cplxf>(), c->box_elems(), c->P + 1, d.as<double>(), c->stream), "norms");
+  else
+    PD_HIP(c, pd::norms2(c->U.as<cplx>(), c->box_elems(), c->P + 1, d.as<double>(), c->stream), "norms");
   PD_HIP(c, hipMemcpyAsync(norms, d.p, sizeof(double) * (c->P + 1), hipMemcpyDeviceToHost, c->stream), "copy");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
   for (int n = 0; n <= c->P; ++n) norms[n] = std::sqrt(norms[n]);

@@ -73,6 +73,7 @@ pd_status pd_steps_dev_noalloc(pd_ctx* c, const double* t0, int batch, double dt
   if (batch < 0 || batch > 65535) return fail(c, PD_EINVAL, "batch must be in [0, 65535]");
   if (batch == 0) return PD_OK;
   if (!t0 || !d_in || !d_out) return fail(c, PD_EINVAL, "null pointer argument");
+  if (c->prec == PD_C64) return fail(c, PD_EINVAL, "the static-workspace call is complex128 only");
   if (n_steps < 1) return fail(c, PD_EINVAL, "n_steps must be >= 1");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(c, PD_EINVAL, "dt must be positive");
   for (int f = 0; f < batch; ++f)
