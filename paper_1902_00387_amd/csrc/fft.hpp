@@ -55,13 +55,12 @@ __device__ __forceinline__ cplx czero() { return {0.0, 0.0}; }
 template <class C>
 __device__ __forceinline__ C zero_of() { return {0, 0}; }
 
-// LDS index padding: one extra 16-byte slot every 2^PAD_SHIFT entries spreads
-// the power-of-two strides of the Stockham scatter over the 64 LDS banks
-// (every 16 entries for N >= 64, every 8 below; chosen with a bank model of
-// the exchange patterns).
+// LDS index padding: one extra slot every 8 entries spreads the power-of-two
+// strides of the Stockham scatter (consecutive lanes writing 8 entries
+// apart in the first pass) over the LDS banks.
 template <int N>
 struct LdsSpan {
-  static constexpr int shift = N >= 64 ? 4 : 3;
+  static constexpr int shift = 3;
   static constexpr int value = N + (N >> shift);
 };
 template <int N>

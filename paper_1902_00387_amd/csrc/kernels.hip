@@ -244,24 +244,28 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
   twr.load(j, tw);
   // each lane issues a chunk of CH tile loads before the chunk's LDS
   // stores, so the workgroup waits for global memory once a chunk, not once
-  // per element (CH bounded by register pressure)
-  constexpr int NIT = (3 * M * TX + nthr - 1) / nthr;
+  // per element (CH bounded by register pressure).  The three components'
+  // rows are consecutive rows R = c M + r of both T1 and the tile; lane
+  // `tid` takes column cc = tid % TX of rows tid / TX + q RPL.
+  static_assert((TX & (TX - 1)) == 0 && nthr % TX == 0, "power-of-two tile width");
+  constexpr int RPL = nthr / TX;                     // rows a pass
+  constexpr int NIT = (3 * M + RPL - 1) / RPL;       // passes
+  const int cc = tid % TX, R0 = tid / TX;
+  const bool cin = x0 + cc < N;
+  const C* src = T1 + (size_t)R0 * N + x0 + cc;
+  C* tl = tile + R0 * TP + cc;
 #pragma unroll 1
   for (int i0 = 0; i0 < NIT; i0 += CH) {
     C buf[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      const int i = tid + (i0 + q) * nthr;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      buf[q] = (i0 + q < NIT && i < 3 * M * TX && x0 + cc < N) ? T1[(c * M + r) * N + x0 + cc] : zero_of<C>();
+      const int R = R0 + (i0 + q) * RPL;
+      buf[q] = (i0 + q < NIT && R < 3 * M && cin) ? src[(size_t)(i0 + q) * RPL * N] : zero_of<C>();
     }
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      const int i = tid + (i0 + q) * nthr;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      if (i0 + q < NIT && i < 3 * M * TX) tile[c * TS + r * TP + cc] = buf[q];
+      const int R = R0 + (i0 + q) * RPL;
+      if (i0 + q < NIT && R < 3 * M) tl[(i0 + q) * RPL * TP] = buf[q];
     }
   }
   __syncthreads();
@@ -310,22 +314,19 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
       }
   }
   __syncthreads();
+  C* dst = T2 + (size_t)R0 * N + x0 + cc;
 #pragma unroll 1
   for (int i0 = 0; i0 < NIT; i0 += CH) {
     C buf[CH];
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      const int i = tid + (i0 + q) * nthr;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      buf[q] = (i0 + q < NIT && i < 3 * M * TX) ? tile[c * TS + r * TP + cc] : zero_of<C>();
+      const int R = R0 + (i0 + q) * RPL;
+      buf[q] = (i0 + q < NIT && R < 3 * M) ? tl[(i0 + q) * RPL * TP] : zero_of<C>();
     }
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      const int i = tid + (i0 + q) * nthr;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      if (i0 + q < NIT && i < 3 * M * TX && x0 + cc < N) T2[(c * M + r) * N + x0 + cc] = buf[q];
+      const int R = R0 + (i0 + q) * RPL;
+      if (i0 + q < NIT && R < 3 * M && cin) dst[(size_t)(i0 + q) * RPL * N] = buf[q];
     }
   }
   __syncthreads();
@@ -421,8 +422,9 @@ __global__ __launch_bounds__(TX * (N / E)) void k_cols_pf(FieldBatch fb, Problem
   constexpr int LANES = TX * T;
   constexpr int TP = TX + 1, TS = M * TP;
   constexpr int NTX = N / TX;  // column tiles a field
-  constexpr int NIT = (3 * M * TX + LANES - 1) / LANES;
-  static_assert(N % TX == 0, "column tiles must cover the grid");
+  constexpr int RPL = LANES / TX;                // rows a pass (rows R = c M + r)
+  constexpr int NIT = (3 * M + RPL - 1) / RPL;
+  static_assert(N % TX == 0 && (TX & (TX - 1)) == 0, "column tiles must cover the grid");
   __shared__ cplx tile[tile_elems<N, E>(LANES)];
   const int nf = fb.count != nullptr ? *fb.count : nfields;
   const int total = nf * NTX;
@@ -437,15 +439,12 @@ __global__ __launch_bounds__(TX * (N / E)) void k_cols_pf(FieldBatch fb, Problem
     const int row = t / NTX;
     return fb.map != nullptr ? (size_t)fb.map[row] : (size_t)row;
   };
+  const int cc0 = tid % TX, R0 = tid / TX;
   auto gload = [&](int t) {
-    const cplx* src = fb.T1 + field_of(t) * rows + (t % NTX) * TX;
+    const cplx* src = fb.T1 + field_of(t) * rows + (t % NTX) * TX + (size_t)R0 * N + cc0;
 #pragma unroll
-    for (int q = 0; q < NIT; ++q) {
-      const int i = tid + q * LANES;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      buf[q] = i < 3 * M * TX ? src[(c * M + r) * N + cc] : czero();
-    }
+    for (int q = 0; q < NIT; ++q)
+      buf[q] = R0 + q * RPL < 3 * M ? src[(size_t)q * RPL * N] : czero();
   };
   int t = blockIdx.x;
   if (t < total) gload(t);
@@ -453,12 +452,8 @@ __global__ __launch_bounds__(TX * (N / E)) void k_cols_pf(FieldBatch fb, Problem
     const size_t f = field_of(t);
     const int x0 = (t % NTX) * TX;
 #pragma unroll
-    for (int q = 0; q < NIT; ++q) {
-      const int i = tid + q * LANES;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      if (i < 3 * M * TX) tile[c * TS + r * TP + cc] = buf[q];
-    }
+    for (int q = 0; q < NIT; ++q)
+      if (R0 + q * RPL < 3 * M) tile[(R0 + q * RPL) * TP + cc0] = buf[q];
     __syncthreads();
     cplx w[3][E];
 #pragma unroll
@@ -503,14 +498,10 @@ __global__ __launch_bounds__(TX * (N / E)) void k_cols_pf(FieldBatch fb, Problem
         if (ky >= -K && ky <= K) tile[c * TS + (ky + K) * TP + g] = w[c][e];
       }
     __syncthreads();
-    cplx* dst = fb.T2 + f * rows + x0;
+    cplx* dst = fb.T2 + f * rows + x0 + (size_t)R0 * N + cc0;
 #pragma unroll
-    for (int q = 0; q < NIT; ++q) {
-      const int i = tid + q * LANES;
-      const int c = i / (M * TX), rem = i - c * (M * TX);
-      const int r = rem / TX, cc = rem - r * TX;
-      if (i < 3 * M * TX) dst[(c * M + r) * N + cc] = tile[c * TS + r * TP + cc];
-    }
+    for (int q = 0; q < NIT; ++q)
+      if (R0 + q * RPL < 3 * M) dst[(size_t)q * RPL * N] = tile[(R0 + q * RPL) * TP + cc0];
     __syncthreads();
   }
 }
