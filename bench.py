@@ -312,7 +312,10 @@ def run_learned(args):
     serial_s = time.perf_counter() - ts
     fine_norm_T = float(torch.linalg.vector_norm(u).item())
     print(f"# serial fine solve {serial_s:.2f} s, |b(T)| = {fine_norm_T:.3e}", file=sys.stderr, flush=True)
-    nc, dtc = coarse_choice(ctx, w, b0, fine_norm_T)
+    if args.lg_nc > 0:
+        nc, dtc = args.lg_nc, args.lg_dtc
+    else:
+        nc, dtc = coarse_choice(ctx, w, b0, fine_norm_T)
     ctx.set_time(T, P, w["dtf"], dtc, nc)
 
     def solve(learned):
@@ -329,32 +332,48 @@ def run_learned(args):
     rp, gp, tp = solve(False)
     Up = ctx.get_slices_dev()[P].clone()
     print(f"# plain G: k_con {rp['k_con']} in {tp:.2f} s", file=sys.stderr, flush=True)
-    # training pairs from the fine and coarse propagators
+    # training pairs from the fine and coarse propagators: seeded random
+    # fields (diverse inputs for a linear map) and the coarse inputs of
+    # plain-G Parareal runs from two more initial fields (iteration k of a run
+    # contributes U^k_n - U^{k-1}_n, n >= k)
     rng = np.random.default_rng(w["seed"] + 1)
     ctx.lg_init(4, w["seed"])
     tg = time.perf_counter()
-    n_fields = 512
+    n_fields = args.lg_random
     for a in range(0, n_fields, 64):
         D = np.stack([initial_field(N, w["kz"], w["seed"] + 10 + i, amp=1.0,
-                                    kmax=float(rng.uniform(2.0, 40.0))) for i in range(a, a + 64)])
+                                    kmax=float(rng.uniform(2.0, 40.0)))
+                      for i in range(a, min(a + 64, n_fields))])
         tt = rng.integers(0, P, D.shape[0]) * (T / P)
         ctx.lg_add_samples(tt, torch.from_numpy(D).to(dev))
+    H = args.lg_harvest
+    block = P * (H + 1) - H * (H + 1) // 2           # samples of one harvested run
+    starts = []
     for r in range(2):
         ctx.set_coarse(False)
         ctx.set_initial(torch.from_numpy(initial_field(N, w["kz"], w["seed"] + 1000 + r)).to(dev))
-        n_samples = ctx.lg_add_parareal_samples(3)
+        starts.append(n_fields + r * block)
+        n_samples = ctx.lg_add_parareal_samples(H)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - tg
     print(f"# {n_samples} training pairs in {gen_s:.1f} s", file=sys.stderr, flush=True)
-    n_val = 64
+    steps = args.lg_steps
+    if args.lg_late > 0:
+        # only the differences of iterations k >= K0: the error that persists
+        K0 = args.lg_late
+        skip = P + (K0 - 1) * P - (K0 - 1) * K0 // 2
+        tr0, trn = starts[0] + skip, block - skip
+        va0, van = starts[1] + skip, min(64, block - skip)
+    else:
+        tr0, trn = 0, n_samples - 64
+        va0, van = n_samples - 64, 64
     ttr = time.perf_counter()
-    val0 = ctx.lg_loss(n_samples - n_val, n_val)
-    steps = 1500
-    losses = ctx.lg_train(0, n_samples - n_val, steps, 8, 1e-3, seed=5)
-    val1 = ctx.lg_loss(n_samples - n_val, n_val)
+    val0 = ctx.lg_loss(va0, van)
+    losses = ctx.lg_train(tr0, trn, steps, 8, 1e-3, seed=5)
+    val1 = ctx.lg_loss(va0, van)
     train_s = time.perf_counter() - ttr
-    print(f"# training {steps} steps {train_s:.1f} s: held-out loss {val0:.3f} -> {val1:.3f}",
-          file=sys.stderr, flush=True)
+    print(f"# training {steps} steps on {trn} pairs {train_s:.1f} s: held-out loss "
+          f"{val0:.3f} -> {val1:.3f}", file=sys.stderr, flush=True)
     solve(True)
     rl, gl, tl = solve(True)
     Ul = ctx.get_slices_dev()[P]
@@ -377,7 +396,8 @@ def run_learned(args):
                     "sigma": rl["sigma"][:rl["iters"]], "final_state_reldiff_vs_plain": diff},
         "serial_fine_gpu_s": serial_s,
         "speedup_vs_serial": {"plain": serial_s / tp, "learned": serial_s / tl},
-        "training": {"pairs": n_samples, "generate_s": gen_s, "train_s": train_s, "steps": steps,
+        "training": {"pairs": n_samples, "trained_on": [tr0, trn], "held_out": [va0, van],
+                     "generate_s": gen_s, "train_s": train_s, "steps": steps,
                      "batch": 8, "held_out_loss": [val0, val1], "last_batch_loss": losses[-1]},
     }
     print(json.dumps(out), flush=True)
@@ -999,6 +1019,15 @@ def main():
                     help="a whole Parareal solve of the 128^2, 64-slice workload as the step")
     ap.add_argument("--parareal5", action="store_true",
                     help="Parareal solves of the default workload (plain coarse propagator)")
+    ap.add_argument("--lg-nc", type=int, default=0,
+                    help="--learned: coarse grid of the base propagator (0: pre-check choice)")
+    ap.add_argument("--lg-dtc", type=float, default=1e-2, help="--learned: base coarse step")
+    ap.add_argument("--lg-random", type=int, default=0, help="--learned: random training fields")
+    ap.add_argument("--lg-harvest", type=int, default=16,
+                    help="--learned: plain-G Parareal iterations harvested per run")
+    ap.add_argument("--lg-late", type=int, default=4,
+                    help="--learned: train only on differences of iterations >= this (0: all)")
+    ap.add_argument("--lg-steps", type=int, default=2000, help="--learned: Adam steps")
     ap.add_argument("--c64", action="store_true",
                     help="complex64 variant beside complex128 (fine step, 128^2 Parareal)")
     ap.add_argument("--p5-nc", type=int, default=128, help="--parareal5: coarse grid")

@@ -256,8 +256,8 @@ pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
    chunks 0 or 1: every fine sweep, then the coarse sweep, on the context's
    stream.  Both orders give bitwise the same iterates,
    defects and k_con; the timings in pd_report add kernel times per stream
-   (they overlap when pipelined).  The learned coarse propagator always runs
-   unpipelined. */
+   (they overlap when pipelined).  The learned coarse propagator (difference
+   form) is pipelined the same way, its serial sweep run by run. */
 pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate);
 
 /* Checkpoint and resume.  After k iterations of pd_parareal the whole state

@@ -137,6 +137,8 @@ pd_status upload_twiddles(pd_ctx* c, int N, DevBuf& d64, DevBuf& d32, hipStream_
 // learned coarse propagator (lg.cpp)
 void lg_release(pd_ctx* c);
 pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st);
+pd_status lg_sweep_range(pd_ctx* c, int a, int b, int n0, bool initial, bool defect,
+                         hipStream_t st);
 // pipelined Parareal with the plain coarse propagator (pipeline.cpp)
 pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep);
 

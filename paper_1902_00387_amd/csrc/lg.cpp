@@ -146,11 +146,15 @@ void lg_release(pd_ctx* c) {
   g.Bcap = 0;
 }
 
-// Serial coarse sweep with the learned propagator over slices n0..P-1.
-// initial: U_{n+1} = G_learned(U_n); otherwise the difference form with the
-// previous iterate in lg.uold (filled here before the sweep) and the fine
-// results in Fo; the defect sums go to c->red.
-pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st) {
+// Serial coarse sweep with the learned propagator over slices [a, b).
+// initial: U_{n+1} = G_learned(U_n); otherwise the difference form
+// U_{n+1} = F_n + G_learned(U_n - Uold_n), with the fine results in Fo and
+// the previous iterate in lg.uold: the states this range overwrites, U_{a+1}
+// .. U_b (and U_a when a = n0, the first slice swept), are copied there
+// first, so the ranges of one sweep may run one after another.  With
+// `defect` (after the last range, b = P) the defect sums go to c->red.
+pd_status lg_sweep_range(pd_ctx* c, int a, int b, int n0, bool initial, bool defect,
+                         hipStream_t st) {
   auto& g = c->lg;
   const size_t box = c->box_elems();
   const int P = c->P;
@@ -161,16 +165,18 @@ pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st) {
   PD_HIP(c, g.Dn.ensure(sizeof(cplx) * box * 2), "alloc");
   PD_HIP(c, g.gn.ensure(sizeof(cplx) * box), "alloc");
   PD_HIP(c, g.nrm.ensure(sizeof(double) * 2), "alloc");
-  if (!initial)
-    PD_HIP(c, hipMemcpyAsync(g.uold.as<cplx>() + (size_t)n0 * box, U + (size_t)n0 * box,
-                             sizeof(cplx) * box * (P + 1 - n0), hipMemcpyDeviceToDevice, st),
+  if (!initial && a < b) {
+    const int lo = a == n0 ? a : a + 1;
+    PD_HIP(c, hipMemcpyAsync(g.uold.as<cplx>() + (size_t)lo * box, U + (size_t)lo * box,
+                             sizeof(cplx) * box * (b + 1 - lo), hipMemcpyDeviceToDevice, st),
            "copy");
+  }
   const pd::nn::Net net = net_of(c, g.params);
   std::vector<float*> h, y;
   act_ptrs(c, 1, h, y);
   float* xw = g.dhA.as<float>();  // features of one field ([Q][12] <= [Q][CH])
   cplx* D = g.Dn.as<cplx>();      // [D, g_scratch]: coarse_one reads D, writes D + box
-  for (int n = n0; n < P; ++n) {
+  for (int n = a; n < b; ++n) {
     PD_HIP(c, pd::nn::sub(U + (size_t)n * box, initial ? nullptr : g.uold.as<cplx>() + (size_t)n * box,
                           D, box, st), "sub");
     PD_HIP(c, pd::norms2(D, box, 1, g.nrm.as<double>(), st), "norm");
@@ -183,10 +189,15 @@ pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st) {
                               g.nrm.as<double>(), U + (size_t)(n + 1) * box, g.Q, !initial, st),
            "combine");
   }
-  if (!initial)
+  if (!initial && defect)
     PD_HIP(c, pd::nn::defect(U + (size_t)P * box, g.uold.as<cplx>() + (size_t)P * box, box,
                              c->red.as<double>(), st), "defect");
   return PD_OK;
+}
+
+// the whole sweep over slices n0..P-1 in one range
+pd_status lg_sweep(pd_ctx* c, int n0, bool initial, hipStream_t st) {
+  return lg_sweep_range(c, n0, c->P, n0, initial, true, st);
 }
 
 }  // namespace ctxh

@@ -52,7 +52,8 @@ pd_status ensure_pipeline_streams(pd_ctx* c) {
 // resumes after iteration kres with U and Gold already loaded.  CT: the
 // context's complex type (complex128 or complex64).
 template <class CT>
-static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep) {
+static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, bool learned,
+                             pd_report* rep) {
   const auto wall0 = std::chrono::steady_clock::now();
   pd_status s = ensure_pipeline_streams(c);
   if (s != PD_OK) return s;
@@ -104,7 +105,17 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, pd_r
   sa.nsteps = c->nc;
   const pd::Problem pc = make_problem(c, c->dtc, c->scheme_c),
                     pf = make_problem(c, c->dtf, c->scheme_f);
-  auto sweep = [&]() -> hipError_t {
+  // one run of the serial coarse sweep over slices [sa.n0, sa.P): the plain
+  // propagator, or the learned one in difference form (n0 = the first slice
+  // the iteration sweeps; defect sums when sa.red is set)
+  pd_status lg_status = PD_OK;
+  auto sweep_k = [&](int n0) -> hipError_t {
+    if constexpr (sizeof(CT) == sizeof(cplx)) {
+      if (learned) {
+        lg_status = lg_sweep_range(c, sa.n0, sa.P, n0, sa.mode == 0, sa.red != nullptr, cs);
+        return lg_status == PD_OK ? hipSuccess : hipErrorUnknown;
+      }
+    }
     return coarse_sweep(c, sa, pc, cs);
   };
 
@@ -125,7 +136,8 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, pd_r
       sa.n0 = lo(ch);
       sa.P = hi(ch);
       sa.red = nullptr;
-      PD_HIP(c, sweep(), "coarse sweep");
+      const hipError_t e = sweep_k(0);
+      if (e != hipSuccess) return lg_status != PD_OK ? lg_status : hipfail(c, e, "coarse sweep");
     }
     PD_HIP(c, hipEventRecord(Ge(k0, ch), cs), "event");
   }
@@ -191,7 +203,8 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, pd_r
         sa.n0 = a;
         sa.P = b;
         sa.red = ch == C - 1 ? c->red.as<double>() : nullptr;
-        PD_HIP(c, sweep(), "coarse sweep");
+        const hipError_t e = sweep_k(n0);
+        if (e != hipSuccess) return lg_status != PD_OK ? lg_status : hipfail(c, e, "coarse sweep");
       }
       PD_HIP(c, hipEventRecord(Ge(k, ch), cs), "event");
     }
@@ -250,8 +263,9 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, pd_r
 }
 
 pd_status parareal_pipelined(pd_ctx* c, double tol, int max_iter, int kres, pd_report* rep) {
-  return c->prec == PD_C64 ? pipelined_t<cplxf>(c, tol, max_iter, kres, rep)
-                           : pipelined_t<cplx>(c, tol, max_iter, kres, rep);
+  const bool learned = c->lg.enabled && c->lg.init;
+  return c->prec == PD_C64 ? pipelined_t<cplxf>(c, tol, max_iter, kres, false, rep)
+                           : pipelined_t<cplx>(c, tol, max_iter, kres, learned, rep);
 }
 
 }  // namespace ctxh

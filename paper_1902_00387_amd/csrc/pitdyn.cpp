@@ -837,7 +837,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
     pd_status rs = ensure_rk_buffers(c);
     if (rs != PD_OK) return rs;
   }
-  if (!learned && c->pipe_chunks > 1) return parareal_pipelined(c, tol, max_iter, kres, rep);
+  if (c->pipe_chunks > 1) return parareal_pipelined(c, tol, max_iter, kres, rep);
   if (c->prec == PD_C64) return parareal_plain<cplxf>(c, tol, max_iter, kres, false, rep, wall0);
   return parareal_plain<cplx>(c, tol, max_iter, kres, learned, rep, wall0);
 }

@@ -1,5 +1,5 @@
 """GPU parity of the batched-instances path (pd_batch_*): uneven instances
-(grid 32..128, both flows, per-instance Rm and kz, coarse boxes held in LDS
+(grid 32..256, both flows, per-instance Rm and kz, coarse boxes held in LDS
 and in global memory) against the FP64 oracle, graph replay against eager
 launches (bitwise), and per-instance convergence against single-instance
 contexts."""
@@ -20,6 +20,9 @@ INSTANCES = [
     ("roberts", 20.0, 1.0, 64, 2.0, 4, 5e-3, 2.5e-2, 64),
     ("gp", 80.0, 0.4, 128, 0.4, 2, 4e-3, 2e-2, 128),
     ("gp", 500.0, 0.3, 32, 1.0, 4, 5e-3, 2.5e-2, 32),
+    # a 256^2 instance (the largest class of the mixed workload) with its
+    # 128^2 coarse box stepped from global memory
+    ("gp", 300.0, 0.7, 256, 0.05, 2, 2.5e-3, 2.5e-3, 128),
 ]
 
 

@@ -100,3 +100,30 @@ def test_pipelined_with_autotuned_launch_shapes_is_bitwise(lib):
     assert r0["k_con"] == r1["k_con"] > 0
     assert r0["sigma"][:r0["iters"]] == r1["sigma"][:r1["iters"]]
     assert np.array_equal(U0, U1)
+
+
+def test_pipelined_learned_coarse_is_bitwise(lib):
+    """The learned coarse propagator (difference form) run by run in the
+    pipelined schedule gives bitwise the iterates, defects and k_con of the
+    plain order."""
+    N, P = 32, 8
+    b0 = initial_field(N, 0.57, 14)
+    res = []
+    for chunks in (0, 2, 3):
+        with lib.Context(0) as ctx:
+            ctx.set_problem("gp", 40.0, 0.57, N)
+            ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, 16)
+            ctx.lg_init(2, 7)
+            p = ctx.lg_params()
+            rng = np.random.default_rng(3)
+            p[-32 * 6:] = (rng.standard_normal(32 * 6) * 0.05).astype(np.float32)
+            ctx.lg_set_params(p)
+            ctx.set_coarse(True)
+            ctx.set_pipeline(chunks, 2)
+            ctx.set_initial(b0)
+            r = ctx.parareal(1e-10, P + 1)
+            res.append((r, ctx.get_slices()))
+    for r, U in res[1:]:
+        assert r["k_con"] == res[0][0]["k_con"] > 0
+        assert r["sigma"][:r["iters"]] == res[0][0]["sigma"][:res[0][0]["iters"]]
+        assert np.array_equal(U, res[0][1])
