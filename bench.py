@@ -11,11 +11,17 @@ it (column phase: inverse y-FFT, u x b, forward y-FFT with the 2/3 mask; row
 phase: forward x-FFT, 1/N^2, spectral curl, implicit diffusion solve, SBDF
 update, inverse x-FFT): 512^2 x 256 = 67.1 M mode-steps.
 
+The sweep runs as Parareal runs it: at 512^2 the library blocks it in time,
+groups of 2 slices running all their steps back to back on 3 streams, so a
+group's buffers stay in the memory-side last-level cache between steps; the
+K timed steps are K steps of every slice.
+
 value: fine-propagator mode-steps per second, N^2 * slices * K / (time of K
   steps); the states are resident in HBM before the timed region.
 roofline: 192 B per mode-step (read and write state and history, 3
-  complex128 components, full grid) over the mean duration of the step's two
-  kernels (HIP events on the stream they run on), against 8 TB/s.
+  complex128 components, full grid) over the time of one step of the sweep
+  (HIP events on the launching stream), against 8 TB/s; the two kernels'
+  own durations, launched over the whole batch, are reported beside it.
 
 Other workloads: --config2 (a whole Parareal solve of the 128^2, 64-slice
 workload), --parareal5 (a Parareal solve of the default workload), --batch,
@@ -47,6 +53,7 @@ NC5, DTC5 = 64, 2.5e-3
 ALG_BYTES_PER_MODE_STEP = 192.0    # read + write b and H, 3 x complex128, full grid
 HBM_PEAK_GBS = 8000.0
 CPU_WORKERS_MAX = 16               # a one-GPU machine's share of host cores
+UNBLOCKED_STEPS = 5                # steps timed kernel by kernel before the blocked sweep
 
 
 def box_m(n):
@@ -118,6 +125,42 @@ def kernels_digest():
         with open(os.path.join(ROOT, "paper_1902_00387_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def summarize_trace(trace_csv, steps, fields):
+    """Kernel-trace summary of a blocked fine sweep (--kernel-only
+    --blocked-only): per phase kernel, dispatches over `fields` slices with the
+    groups' size (Grid_Size_Y) and their mean duration, and the span from the
+    first start to the last end of all those dispatches divided by `steps`,
+    the sweep's time a step."""
+    import csv
+    rows = list(csv.DictReader(open(trace_csv)))
+    def kname(r):
+        n = r["Kernel_Name"].split("(")[0]
+        return n[5:] if n.startswith("void ") else n
+    ks = [r for r in rows if kname(r).startswith(("pd::k_cols", "pd::k_rows"))]
+    # the sweep's launches are those over a group: the most frequent grid
+    # height below the whole batch (not the whole-batch start, the autotuner's
+    # launches or a persistent kernel's one-row grid)
+    from collections import Counter
+    ys = Counter(int(r["Grid_Size_Y"]) for r in ks if 1 < int(r["Grid_Size_Y"]) < int(fields))
+    gy = ys.most_common(1)[0][0]
+    ks = [r for r in ks if int(r["Grid_Size_Y"]) == gy]
+    out = {"dispatches": len(ks), "kernels": {}}
+    for r in ks:
+        name = kname(r)
+        d = out["kernels"].setdefault(name, {"calls": 0, "total_us": 0.0, "group": int(r["Grid_Size_Y"])})
+        d["calls"] += 1
+        d["total_us"] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    for d in out["kernels"].values():
+        d["mean_us"] = d["total_us"] / d["calls"]
+    t0 = min(int(r["Start_Timestamp"]) for r in ks)
+    t1 = max(int(r["End_Timestamp"]) for r in ks)
+    out["span_ms"] = (t1 - t0) * 1e-6
+    out["steps"] = int(steps)
+    out["span_ms_per_step"] = out["span_ms"] / int(steps)
+    out["sum_kernel_ms_per_step"] = sum(d["total_us"] for d in out["kernels"].values()) * 1e-3 / int(steps)
+    return out
 
 
 def summarize_pmc(fetch_csv, write_csv, out_path):
@@ -822,23 +865,32 @@ def run_headline(args, cpu):
     (rv, cv), (mr, mc) = tuned
     _log(f"# autotune: rows {pd.variants(N5, 0)[rv]} {mr*1e3:.0f} us, cols "
          f"{pd.variants(N5, 1)[cv]} {mc*1e3:.0f} us")
+    group, nstreams = ctx.fine_blocking()
+    # the step's two kernels one at a time over the whole batch (unblocked)
+    KS = UNBLOCKED_STEPS
+    ctx.set_fine_blocking(0)
+    ctx.fine_sweep_steps(0, 1)
+    mk = ctx.fine_sweep_steps(1, KS, timed=True)
+    ms_cols, ms_rows = mk[0] / KS, mk[1] / KS
+    # the sweep as Parareal runs it (blocked in groups of fields when the
+    # library's default says so), continued from there
+    ctx.set_fine_blocking(-1)
+    s0 = 1 + KS
     if args.warmup > 0:
-        for a, c in _sweep_chunks(0, args.warmup, nf):
+        for a, c in _sweep_chunks(s0, args.warmup, nf):
             ctx.fine_sweep_steps(a, c)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms = [0.0, 0.0, 0.0]
-    for a, c in _sweep_chunks(args.warmup, args.steps, nf):
-        m = ctx.fine_sweep_steps(a, c, timed=True)
-        ms = [x + y for x, y in zip(ms, m)]
+    ms_all = 0.0
+    for a, c in _sweep_chunks(s0 + args.warmup, args.steps, nf):
+        ms_all += ctx.fine_sweep_steps(a, c, timed=True)[2]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     K = args.steps
     modes = N5 * N5 * P5
-    ms_cols, ms_rows = ms[0] / K, ms[1] / K
     value = modes * K / elapsed
-    step_s = (ms_cols + ms_rows) * 1e-3
-    achieved = ALG_BYTES_PER_MODE_STEP * modes / step_s / 1e9
+    step_ms = ms_all / K
+    achieved = ALG_BYTES_PER_MODE_STEP * modes / (step_ms * 1e-3) / 1e9
     cols_b, rows_b = kernel_bytes(N5, P5)
     rname = "k_rows<512,%d,%d,0,%s>" % (pd.variants(N5, 0)[rv][0], abs(pd.variants(N5, 0)[rv][1]),
                                         "true" if pd.variants(N5, 0)[rv][1] < 0 else "false")
@@ -847,8 +899,12 @@ def run_headline(args, cpu):
     tr_c = measured_traffic("pd::" + cname, TRAFFIC_FILE5)
     tr_r = measured_traffic("pd::" + rname, TRAFFIC_FILE5)
     traffic = tr_c + tr_r if tr_c is not None and tr_r is not None else None
-    _log(f"# {K} steps: {elapsed*1e3/K:.3f} ms/step wall, kernels cols {ms_cols:.3f} + rows "
-         f"{ms_rows:.3f} ms; {value:.3e} mode-steps/s; {achieved:.0f} GB/s algorithmic")
+    sched = (f"blocked: groups of {group} fields on {nstreams} streams" if group > 0
+             else "unblocked: every step over all 256 slices")
+    _log(f"# unblocked kernels: cols {ms_cols:.3f} + rows {ms_rows:.3f} ms = "
+         f"{ms_cols + ms_rows:.3f} ms a step")
+    _log(f"# {K} steps, {sched}: {step_ms:.3f} ms/step (HIP events), {elapsed*1e3/K:.3f} ms/step "
+         f"wall; {value:.3e} mode-steps/s; {achieved:.0f} GB/s algorithmic")
     out = {
         "metric": "fine-propagator mode-steps/sec (batched F over all slices) & HBM GB/s",
         "value": value, "unit": "mode-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -860,21 +916,27 @@ def run_headline(args, cpu):
                                "complex128, T=256 over 256 slices, fine SBDF2 dt=5e-4 (2000 "
                                "steps a slice); one step = one fine step of all 256 slices",
                    "N": N5, "slices": P5, "dt_fine": DT5, "fine_steps_per_slice": nf,
-                   "mode_steps_per_step": modes},
-        "roofline": {"bound": "hbm", "kernel": f"fine step: {cname} + {rname}",
+                   "mode_steps_per_step": modes, "schedule": sched},
+        "roofline": {"bound": "hbm", "kernel": f"fine step ({cname} + {rname}), {sched}",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "note": "achieved = 192 B x 67.1 M mode-steps / (mean column-phase + "
-                             "row-phase kernel duration); traffic = FETCH_SIZE + WRITE_SIZE of "
-                             "both kernels per step, scaled by the same counters on a 1 GiB "
-                             "copy (profiles/traffic_gp512_p256.json), null if the kernels "
-                             "changed since"},
+                     "note": "achieved = 192 B x 67.1 M mode-steps / time of one step of the "
+                             "sweep (HIP events on the launching stream around the K timed "
+                             "steps; in the blocked sweep the kernels of different groups "
+                             "overlap on the streams, so the step time is their joint span); "
+                             "traffic = FETCH_SIZE + WRITE_SIZE of the two unblocked launches "
+                             "of one step (bytes between L2 and memory, of which the memory-side "
+                             "cache serves part in the blocked sweep), scaled by the same "
+                             "counters on a 1 GiB copy (profiles/traffic_gp512_p256.json), null "
+                             "if the kernels changed since"},
         "kernels": {
+            "unblocked_steps": KS,
             "cols": {"name": cname, "ms": ms_cols, "design_bytes": cols_b,
                      "design_gbs": cols_b / (ms_cols * 1e-3) / 1e9},
             "rows": {"name": rname, "ms": ms_rows, "design_bytes": rows_b,
                      "design_gbs": rows_b / (ms_rows * 1e-3) / 1e9},
             "design_bytes_per_mode_step": (cols_b + rows_b) / modes,
+            "blocked_ms_per_step": step_ms,
         },
     }
     if cpu is not None:
@@ -950,6 +1012,11 @@ def run_kernel_only5(args):
     import paper_1902_00387_amd as pd
     nf = int(round(T5 / P5 / DT5))
     ctx, _ = headline_context(pd)
+    if args.blocked_only:
+        ctx.set_fine_blocking(-1)
+    else:
+        # whole-batch launches: one dispatch per kernel and step
+        ctx.set_fine_blocking(0)
     for a, c in _sweep_chunks(0, args.warmup + args.steps, nf):
         ctx.fine_sweep_steps(a, c)
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -959,6 +1026,59 @@ def run_kernel_only5(args):
     ctx.close()
     print(json.dumps({"kernel_only": True, "steps": args.warmup + args.steps,
                       "copy_bytes_each_way": src.numel() * 8}), flush=True)
+
+
+BLOCKING_CASES = (  # N, slices, Rm, fine dt, T, coarse dt (coarse grid 64^2)
+    (512, 256, 2000.0, 5e-4, 256.0, 2.5e-3),
+    (256, 128, 500.0, 1e-3, 64.0, 5e-3),
+    (128, 64, 100.0, 2e-3, 64.0, 1e-2),
+)
+BLOCKING_SETTINGS = ((0, 1), (1, 3), (2, 3), (3, 3), (4, 3), (6, 3), (8, 3), (16, 3), (2, 2),
+                     (3, 2), (4, 2), (8, 2), (16, 2), (32, 2), (4, 1), (8, 1))
+
+
+def run_blocking_sweep(args):
+    """Time a fine sweep of K steps of every slice for each fine-blocking
+    setting (fields a group, streams) and each launch shape of the two phase
+    kernels, on three grid/batch sizes (the slice states from the seeded field
+    and an initial coarse run)."""
+    import paper_1902_00387_amd as pd
+    K = args.steps
+    out = {"experiment": "fine-sweep blocking", "steps": K, "cases": []}
+    for n, p, rm, dtf, T_, dtc in BLOCKING_CASES:
+        ctx = pd.Context(0)
+        ctx.set_problem("gp", rm, KZ, n)
+        ctx.set_time(T_, p, dtf, dtc, 64)
+        ctx.seed_initial(SEED5, 1e-3, 4.0)
+        ctx.parareal(0.0, 0)
+        nf = int(round(T_ / p / dtf))
+        res = []
+        try:
+            for rv in range(len(pd.variants(n, 0))):
+                for cv in range(len(pd.variants(n, 1))):
+                    pd.select_variant(n, rv, cv)
+                    for g, ns in BLOCKING_SETTINGS:
+                        if g >= p:
+                            continue
+                        ctx.set_fine_blocking(g, ns)
+                        ctx.fine_sweep_steps(0, 2)
+                        ms = 0.0
+                        for a, c in _sweep_chunks(2, K, nf):
+                            ms += ctx.fine_sweep_steps(a, c, timed=True)[2]
+                        r = {"rows": pd.variants(n, 0)[rv], "cols": pd.variants(n, 1)[cv],
+                             "group": g, "streams": ns, "ms_per_step": ms / K,
+                             "mode_steps_per_s": n * n * p / (ms / K * 1e-3)}
+                        res.append(r)
+                        _log(f"# {n}^2 x {p}: rows {r['rows']} cols {r['cols']} group {g} streams "
+                             f"{ns}: {ms / K:.4f} ms a step")
+        finally:
+            pd.select_variant(n, 0, 0)
+        ctx.close()
+        best = min(res, key=lambda r: r["ms_per_step"])
+        unb = min((r for r in res if r["group"] == 0), key=lambda r: r["ms_per_step"])
+        out["cases"].append({"N": n, "slices": p, "results": res, "best": best, "best_unblocked": unb})
+        _log(f"# {n}^2 x {p}: best {best}; best unblocked {unb['ms_per_step']:.4f} ms")
+    print(json.dumps(out), flush=True)
 
 
 def run_parareal5(args):
@@ -1012,8 +1132,11 @@ def run_parareal5(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 100 fine steps; 20 solves with --config2, "
+                         "1 batch run with --batch)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 10, "
+                    "5 with --config2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--config2", action="store_true",
                     help="a whole Parareal solve of the 128^2, 64-slice workload as the step")
@@ -1035,6 +1158,12 @@ def main():
     ap.add_argument("--p5-iters", type=int, default=8, help="--parareal5: iteration cap")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the fine-sweep kernels (for profiler runs)")
+    ap.add_argument("--blocking-sweep", action="store_true",
+                    help="time the fine sweep for fine-blocking settings and launch shapes")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_CSV", "STEPS", "FIELDS"),
+                    help="summarize a kernel trace of --kernel-only --blocked-only")
+    ap.add_argument("--blocked-only", action="store_true",
+                    help="--kernel-only: the blocked sweep instead of whole-batch launches")
     ap.add_argument("--batch", action="store_true",
                     help="the many-instance workload instead of the single solve")
     ap.add_argument("--batch-scale", type=float, default=1.0)
@@ -1059,6 +1188,9 @@ def main():
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(*args.summarize_pmc)))
         return
+    if args.summarize_trace:
+        print(json.dumps(summarize_trace(*args.summarize_trace), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the Parareal "
               "path here is single-GPU (slices would shard across GPUs in contiguous blocks).", file=sys.stderr)
@@ -1071,7 +1203,11 @@ def main():
 
     default = not (args.batch or args.learned or args.nc_sweep or args.nc_sweep_gp or
                    args.work_precision or args.table1 or args.config2 or args.parareal5 or
-                   args.kernel_only or args.c64)
+                   args.kernel_only or args.c64 or args.blocking_sweep)
+    if args.steps is None:
+        args.steps = 1 if args.batch else 20 if args.config2 or args.kernel_only else 100
+    if args.warmup is None:
+        args.warmup = 5 if args.config2 or args.kernel_only else 10
     # the CPU baseline forks its workers before anything touches the GPU
     cpu = cpu_baseline() if default and not args.no_cpu_baseline else None
     if cpu is not None:
@@ -1103,6 +1239,9 @@ def main():
         return
     if args.parareal5:
         run_parareal5(args)
+        return
+    if args.blocking_sweep:
+        run_blocking_sweep(args)
         return
     run_headline(args, cpu)
 

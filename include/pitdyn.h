@@ -260,6 +260,27 @@ pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
    form) is pipelined the same way, its serial sweep run by run. */
 pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate);
 
+/* Temporal blocking of the batched fine propagator F (Section 3: the fine
+   solves of the slices are independent, so their order is free).  group > 0:
+   fields are taken in consecutive groups of `group`; each group runs all its
+   fine steps before the next group on its stream starts, and the groups are
+   dealt round-robin to `streams` streams (1..3: the context's stream and the
+   two streams of the pipelined schedule, idle outside it), so a group's
+   state, history and row buffers stay in the device's last-level cache
+   across its steps instead of streaming through HBM at every step.
+   group = 0: off (every step runs over the whole batch); group = -1
+   (default): groups of 2 fields on 3 streams at 512^2, of 16 fields on 2
+   streams at 256^2, off on smaller grids.  Applies to the multi-launch path (fine sweeps of pd_parareal,
+   pd_fine_dev / pd_steps_dev batches, pd_fine_sweep_steps, pd_profile_fine);
+   in the pipelined schedule each run of slices is blocked on its own fine
+   stream in groups holding about as many fields in flight.  Results are
+   bitwise the same as unblocked.  PD_EINVAL for group < -1, or group > 0
+   with streams outside [1, 3]. */
+pd_status pd_set_fine_blocking(pd_ctx* ctx, int group, int streams);
+/* The blocking in effect for the context's slice batch: fields a group (0:
+   unblocked) and streams.  PD_ESTATE before pd_set_time. */
+pd_status pd_get_fine_blocking(pd_ctx* ctx, int* group, int* streams);
+
 /* Checkpoint and resume.  After k iterations of pd_parareal the whole state
    of the iteration is the slice states U^k_n (pd_get_slices) and, for the
    plain coarse propagator, the coarse values G(U^k_n), n = 0..P-1
@@ -285,16 +306,19 @@ pd_status pd_profile_fine(pd_ctx* ctx, int reps, double* ms);
 /* The batched fine propagator F (Section 3: the fine solves of all slices run
    in parallel) one step at a time, for measurement: runs fine steps
    [step0, step0 + n_steps) of the fine sweep over all n_slices slices on the
-   context's working slice buffers, exactly the launches pd_parareal makes
-   (one column-phase and one row-phase kernel per step; SBDF2 fine stepper
-   only, else PD_EINVAL).  step0 = 0 starts the sweep from the current slice
+   context's working slice buffers, the launches pd_parareal makes (one
+   column-phase and one row-phase kernel per step, over the whole batch or,
+   with fine blocking in effect, over each group of fields, each group
+   running all n_steps steps before the next on its stream; SBDF2 fine
+   stepper only, else PD_EINVAL).  step0 = 0 starts the sweep from the current slice
    states U_0..U_{P-1} (U itself is not changed); step0 > 0 continues a sweep
    that the previous call on this context left at step0 (else PD_ESTATE);
    step0 + n_steps <= dT/dt_fine.  Any other call that runs the fine
    propagator on the slices ends the stepwise sweep.  ms (may be NULL):
-   ms[0] / ms[1] = summed durations of the column-phase / row-phase kernels,
-   ms[2] = duration of the whole n_steps, in milliseconds, from HIP events on
-   the context's stream.  Returns after the work completes. */
+   ms[0] / ms[1] = summed durations of the column-phase / row-phase kernels
+   (-1 when blocked: the groups' kernels overlap), ms[2] = duration of the
+   whole n_steps, in milliseconds, from HIP events on the context's stream.
+   Returns after the work completes. */
 pd_status pd_fine_sweep_steps(pd_ctx* ctx, int step0, int n_steps, double* ms);
 
 /* Working states of the fine propagator for slices [first, first + count),

@@ -62,7 +62,7 @@ SYMBOLS = [
     "pd_lg_load", "pd_set_pipeline", "pd_set_scheme", "pd_lg_set_loss_decay",
     "pd_seed_field", "pd_seed_initial", "pd_fine_sweep_steps",
     "pd_get_fine_states_dev", "pd_steps_dev_noalloc", "pd_lg_add_feature_samples",
-    "pd_lg_set_operands", "pd_set_precision",
+    "pd_lg_set_operands", "pd_set_precision", "pd_set_fine_blocking", "pd_get_fine_blocking",
 ]
 
 
@@ -163,6 +163,8 @@ def _load():
                                        C.POINTER(i)], i),
         "pd_lg_set_operands": ([vp, i], i),
         "pd_set_precision": ([vp, i], i),
+        "pd_set_fine_blocking": ([vp, i, i], i),
+        "pd_get_fine_blocking": ([vp, C.POINTER(i), C.POINTER(i)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -327,6 +329,17 @@ class Context:
         """Pipelined Parareal over `chunks` runs of slices (0 or 1: off);
         speculate: 0 hold the last run, 1 start every run early, 2 predict."""
         self._ok(lib.pd_set_pipeline(self._h, int(chunks), int(speculate)))
+
+    def set_fine_blocking(self, group: int, streams: int = 3):
+        """Temporal blocking of fine sweeps: groups of `group` fields run all
+        their steps back to back on `streams` streams (0: off, -1: default)."""
+        self._ok(lib.pd_set_fine_blocking(self._h, int(group), int(streams)))
+
+    def fine_blocking(self) -> tuple:
+        """(fields a group or 0, streams) in effect for the slice batch."""
+        g, s = C.c_int(), C.c_int()
+        self._ok(lib.pd_get_fine_blocking(self._h, C.byref(g), C.byref(s)))
+        return g.value, s.value
 
     def get_coarse_values(self) -> np.ndarray:
         out = np.empty((self.P, 3, self.N, self.N), np.complex128)

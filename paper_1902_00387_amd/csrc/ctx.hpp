@@ -23,6 +23,11 @@ struct pd_ctx {
   hipStream_t fst = nullptr;       // pipelined Parareal: fine streams
   int pipe_spec = 2;               // pipelined: which chunks of the next fine sweep start early
   int pipe_chunks = 2;             // slice chunks of the pipelined Parareal (< 2: off)
+  // temporal blocking of fine sweeps on the multi-launch path: groups of blk_g
+  // fields run all their steps back to back, dealt round-robin to blk_s
+  // streams (blk_g < 0: the grid's default, 0: off)
+  int blk_g = -1, blk_s = 0;
+  hipEvent_t bev[3] = {nullptr, nullptr, nullptr};  // fork and joins of the blocked sweep
   std::string err;
   int path = PD_PATH_AUTO;
   int coarse_form = PD_COARSE_AUTO;
@@ -123,6 +128,46 @@ pd_status ensure_rk_buffers(pd_ctx* c);
 bool use_conv_sweep(const pd_ctx* c);
 hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgs& sa, const pd::Problem& pc, hipStream_t st);
 int choose_path(const pd_ctx* c, int nfields);
+// fields a group (0: unblocked) and streams of the blocked fine sweep for a
+// batch of nfields fields
+void fine_blocking(const pd_ctx* c, int nfields, int* group, int* streams);
+// Enqueue `run(sub_batch, fields, stream)` for consecutive groups of `group`
+// fields of fb, dealt round-robin to `streams` streams (st first, then the
+// context's idle pipeline streams), forked from and joined back into st.
+// the streams of a blocked sweep (st first, at most 3) and the fork event
+// recorded on st that the others wait for; returns how many there are
+int blocking_fork(pd_ctx* c, int streams, hipStream_t st, hipStream_t* out, hipError_t* err);
+template <class C, class Fn>
+hipError_t over_groups(pd_ctx* c, const pd::FieldBatchT<C>& fb, int nfields, int group,
+                       int streams, hipStream_t st, Fn&& run) {
+  hipStream_t ss[3];
+  hipError_t e = hipSuccess;
+  const int n = blocking_fork(c, streams, st, ss, &e);
+  if (e != hipSuccess) return e;
+  const size_t box = c->box_elems(), rows = c->rows_elems();
+  int gi = 0;
+  for (int f0 = 0; f0 < nfields; f0 += group, ++gi) {
+    const int ng = nfields - f0 < group ? nfields - f0 : group;
+    pd::FieldBatchT<C> q = fb;
+    q.B += (size_t)f0 * box;
+    q.H += (size_t)f0 * box;
+    q.T1 += (size_t)f0 * rows;
+    q.T2 += (size_t)f0 * rows;
+    if (q.R) q.R += (size_t)4 * f0 * box;
+    if (q.t0) q.t0 += f0;
+    if (q.fRm) q.fRm += f0;
+    if (q.fkz) q.fkz += f0;
+    e = run(q, ng, ss[gi % n]);
+    if (e != hipSuccess) return e;
+  }
+  // join: later work on st follows every group
+  for (int i = 1; i < n; ++i) {
+    e = hipEventRecord(c->bev[i], ss[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, c->bev[i], 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
                       int nsteps, hipStream_t st);
 pd_status check_box_dev(pd_ctx* c, const void* d, int N, size_t nfields, hipStream_t st);

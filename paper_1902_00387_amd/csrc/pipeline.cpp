@@ -168,7 +168,19 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, bool
           if (c->scheme_f != PD_SCHEME_SBDF2) fb.R = c->Rf.as<cplx>() + (size_t)4 * a * box;
         int path = choose_path(c, b - a);
         if (path == PD_PATH_MULTI2) path = PD_PATH_MULTI;  // the chunks already use two streams
-        PD_HIP(c, pd::propagate(c->N, fb, pf, b - a, c->nf, path, st), "fine sweep");
+        // blocked in groups on the chunk's own stream, about as many fields
+        // in flight as the context's blocking keeps on its streams
+        int g = 0, gs = 1;
+        if (path == pd::PATH_MULTI) fine_blocking(c, b - a, &g, &gs);
+        if (g > 0) g = std::max(1, (g * gs + NFS - 1) / NFS);
+        if (g > 0 && g < b - a)
+          PD_HIP(c, over_groups(c, fb, b - a, g, 1, st,
+                                [&](const pd::FieldBatchT<CT>& q, int ng, hipStream_t x) {
+                                  return pd::propagate(c->N, q, pf, ng, c->nf, pd::PATH_MULTI, x);
+                                }),
+                 "fine sweep");
+        else
+          PD_HIP(c, pd::propagate(c->N, fb, pf, b - a, c->nf, path, st), "fine sweep");
       }
       PD_HIP(c, hipEventRecord(Fe(k, ch), st), "event");
     }

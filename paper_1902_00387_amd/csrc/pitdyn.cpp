@@ -5,6 +5,7 @@
 // launches on a stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -136,7 +137,63 @@ int choose_path(const pd_ctx* c, int nfields) {
   return nfields >= 512 ? pd::PATH_SINGLE_WG : pd::PATH_MULTI;
 }
 
-// Fine propagation of a batch on the context's launch path.
+// Temporal blocking of fine sweeps.  A step of the whole batch streams every
+// field's state, history and both row buffers through HBM (213 B a grid mode
+// at 512^2, about 14 GB a step for 256 fields); a group of a few fields that
+// runs all its steps back to back keeps its 28 MB a field (512^2) in the
+// 256 MB memory-side last-level cache from one step to the next, and the
+// phases of groups on different streams overlap.  Defaults measured on
+// MI355X (K steps of every slice, best launch shapes): 512^2 x 256 fields,
+// groups of 2 on 3 streams, 2.74 against 3.46 ms a step unblocked; 256^2 x
+// 128, groups of 16 on 2 streams, 0.353 against 0.405 ms; 128^2 x 64 gains
+// under 10 % (its whole batch, about 200 MB, already fits the cache) and
+// stays unblocked.
+void fine_blocking(const pd_ctx* c, int nfields, int* group, int* streams) {
+  int g = c->blk_g, s = c->blk_s;
+  if (g < 0) {
+    g = c->N >= 512 ? 2 : c->N == 256 ? 16 : 0;
+    s = c->N >= 512 ? 3 : 2;
+  }
+  if (g >= nfields) g = 0;
+  *group = g;
+  *streams = g > 0 ? std::max(1, std::min(s, 3)) : 1;
+}
+
+int blocking_fork(pd_ctx* c, int streams, hipStream_t st, hipStream_t* out, hipError_t* err) {
+  out[0] = st;
+  *err = hipSuccess;
+  if (streams <= 1) return 1;
+  // the pipelined schedule's two extra streams, idle outside it
+  for (hipStream_t* p : {&c->fst, &c->cst})
+    if (!*p && (*err = hipStreamCreateWithFlags(p, hipStreamNonBlocking)) != hipSuccess) return 1;
+  for (auto& ev : c->bev)
+    if (!ev && (*err = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return 1;
+  int n = 1;
+  for (hipStream_t x : {c->fst, c->cst})
+    if (n < streams && x != st) out[n++] = x;
+  if (n > 1) {
+    *err = hipEventRecord(c->bev[0], st);
+    for (int i = 1; i < n && *err == hipSuccess; ++i)
+      *err = hipStreamWaitEvent(out[i], c->bev[0], 0);
+  }
+  return n;
+}
+
+// Fine propagation of a batch on the context's launch path (blocked in groups
+// of fields when the context's blocking says so).
+template <class C>
+static hipError_t fine_batch_t(pd_ctx* c, const pd::FieldBatchT<C>& fb, const pd::Problem& pb,
+                               int nfields, int nsteps, int path, hipStream_t st) {
+  int g = 0, ns = 1;
+  if (path == pd::PATH_MULTI && fb.map == nullptr) fine_blocking(c, nfields, &g, &ns);
+  if (g > 0 && nsteps > 0)
+    return over_groups(c, fb, nfields, g, ns, st,
+                       [&](const pd::FieldBatchT<C>& q, int ng, hipStream_t x) {
+                         return pd::propagate(c->N, q, pb, ng, nsteps, pd::PATH_MULTI, x);
+                       });
+  return pd::propagate(c->N, fb, pb, nfields, nsteps, path, st);
+}
+
 hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb, int nfields,
                       int nsteps, hipStream_t st) {
   const int path = choose_path(c, nfields);
@@ -146,7 +203,7 @@ hipError_t fine_batch(pd_ctx* c, const pd::FieldBatch& fb, const pd::Problem& pb
     if (c->side == nullptr && hipStreamCreate(&c->side) != hipSuccess) return hipErrorOutOfMemory;
     return pd::propagate2(c->N, fb, pb, nfields, nsteps, st, c->side, c->sev);
   }
-  return pd::propagate(c->N, fb, pb, nfields, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st);
+  return fine_batch_t(c, fb, pb, nfields, nsteps, path == PD_PATH_MULTI2 ? 0 : path, st);
 }
 
 // complex64: the convolution sweep (N_C <= 64) or the multi-launch sweep
@@ -162,7 +219,7 @@ hipError_t coarse_sweep(pd_ctx* c, pd::SweepArgsF& sa, const pd::Problem& pc, hi
 
 hipError_t fine_batch(pd_ctx* c, const pd::FieldBatchF& fb, const pd::Problem& pb, int nfields,
                       int nsteps, hipStream_t st) {
-  return pd::propagate(c->N, fb, pb, nfields, nsteps, pd::PATH_MULTI, st);
+  return fine_batch_t(c, fb, pb, nfields, nsteps, pd::PATH_MULTI, st);
 }
 
 pd_status upload_twiddles(pd_ctx* c, int N, DevBuf& d64, DevBuf& d32, hipStream_t st) {
@@ -475,6 +532,37 @@ static pd_status fine_sweep_steps_t(pd_ctx* c, int step0, int n_steps, double* m
     std::vector<hipEvent_t>& e;
     ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }
   } evf{ev};
+  int g = 0, ns = 1;
+  fine_blocking(c, P, &g, &ns);
+  if (g > 0) {
+    // blocked: each group of g fields runs all n_steps steps back to back;
+    // the phases of different groups overlap, so only the whole is timed
+    if (ms) {
+      ev.resize(2, nullptr);
+      for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
+      PD_HIP(c, hipEventRecord(ev[0], st), "event");
+    }
+    PD_HIP(c, over_groups(c, fb, P, g, ns, st,
+                          [&](const pd::FieldBatchT<C>& q, int ng, hipStream_t x) -> hipError_t {
+                            hipError_t e = hipSuccess;
+                            for (int s = step0; s < step0 + n_steps && e == hipSuccess; ++s) {
+                              e = pd::cols(c->N, q, pf, ng, s, x);
+                              if (e == hipSuccess) e = pd::rows(c->N, q, pf, ng, s == 0 ? 1 : 2, 0, x);
+                            }
+                            return e;
+                          }),
+           "blocked steps");
+    if (ms) PD_HIP(c, hipEventRecord(ev[1], st), "event");
+    PD_HIP(c, hipStreamSynchronize(st), "sync");
+    if (ms) {
+      float all = 0.f;
+      PD_HIP(c, hipEventElapsedTime(&all, ev[0], ev[1]), "event");
+      ms[0] = ms[1] = -1.0;
+      ms[2] = all;
+    }
+    c->sweep_next = step0 + n_steps;
+    return PD_OK;
+  }
   if (ms) {
     ev.resize((size_t)2 * n_steps + 1, nullptr);
     for (auto& e : ev) PD_HIP(c, hipEventCreate(&e), "event");
@@ -555,6 +643,8 @@ void pd_destroy(pd_ctx* c) {
       }
     for (auto& e : c->sev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->bev)
+      if (e) (void)hipEventDestroy(e);
     if (c->hred) (void)hipHostFree(c->hred);
     lg_release(c);
     c->tw.release(); c->twc.release(); c->twf.release(); c->twcf.release();
@@ -582,6 +672,24 @@ pd_status pd_set_pipeline(pd_ctx* c, int chunks, int speculate) {
   if (speculate < 0 || speculate > 2) return fail(c, PD_EINVAL, "speculate must be 0, 1 or 2");
   c->pipe_chunks = chunks;
   c->pipe_spec = speculate;
+  return PD_OK;
+}
+
+pd_status pd_set_fine_blocking(pd_ctx* c, int group, int streams) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (group < -1) return fail(c, PD_EINVAL, "group must be -1 (default), 0 (off) or positive");
+  if (group > 0 && (streams < 1 || streams > 3)) return fail(c, PD_EINVAL, "streams must be in [1, 3]");
+  c->blk_g = group;
+  c->blk_s = group > 0 ? streams : 0;
+  return PD_OK;
+}
+
+pd_status pd_get_fine_blocking(pd_ctx* c, int* group, int* streams) {
+  if (!c || !group || !streams) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_time) return fail(c, PD_ESTATE, "pd_set_time not called");
+  fine_blocking(c, c->P, group, streams);
   return PD_OK;
 }
 

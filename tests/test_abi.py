@@ -36,6 +36,8 @@ def test_null_context_calls_fail_cleanly():
     import paper_1902_00387_amd as pd
     assert pd.lib.pd_set_problem(None, 1, 10.0, 1.0, 32) == pd.EINVAL
     assert pd.lib.pd_set_path(None, 0) == pd.EINVAL
+    assert pd.lib.pd_set_fine_blocking(None, 2, 3) == pd.EINVAL
+    assert pd.lib.pd_get_fine_blocking(None, None, None) == pd.EINVAL
     assert pd.lib.pd_last_error(None) == b"null context"
     assert pd.lib.pd_create(None, 0) == pd.EINVAL
 

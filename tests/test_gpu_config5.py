@@ -71,12 +71,20 @@ def test_config5_stepwise_sweep_matches_oracle(lib):
         U = ctx.get_slices_dev()
         start = {n: U[n].cpu().numpy() for n in samples}
         del U
+        assert ctx.fine_blocking() == (2, 3)    # blocked in time by default at 512^2
         ctx.fine_sweep_steps(0, 2)
         ms = ctx.fine_sweep_steps(2, 1, timed=True)
-        assert all(m > 0 for m in ms)
+        assert ms[0] == ms[1] == -1.0 and ms[2] > 0
         for n in samples:
             y = ctx.get_fine_states_dev(n, 1)[0].cpu().numpy()
             ref = stepper.propagate(start[n], "gp", RM, KZ, n * (T / P), DTF, 3)
             assert rel(y, ref) <= TOL, (n, rel(y, ref))
         with pytest.raises(lib.PitdynError):
             ctx.fine_sweep_steps(5, 1)          # the sweep stands at step 3
+        # the same sweep continued with whole-batch launches, kernel by kernel
+        ctx.set_fine_blocking(0)
+        ms = ctx.fine_sweep_steps(3, 1, timed=True)
+        assert all(m > 0 for m in ms)
+        y = ctx.get_fine_states_dev(200, 1)[0].cpu().numpy()
+        ref = stepper.propagate(start[200], "gp", RM, KZ, 200 * (T / P), DTF, 4)
+        assert rel(y, ref) <= TOL, rel(y, ref)
