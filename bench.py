@@ -12,7 +12,7 @@ phase: forward x-FFT, 1/N^2, spectral curl, implicit diffusion solve, SBDF
 update, inverse x-FFT): 512^2 x 256 = 67.1 M mode-steps.
 
 The sweep runs as Parareal runs it: at 512^2 the library blocks it in time,
-groups of 2 slices running all their steps back to back on 3 streams, so a
+groups of 3 slices running all their steps back to back on 3 streams, so a
 group's buffers stay in the memory-side last-level cache between steps; the
 K timed steps are K steps of every slice.
 
@@ -892,8 +892,9 @@ def run_headline(args, cpu):
     step_ms = ms_all / K
     achieved = ALG_BYTES_PER_MODE_STEP * modes / (step_ms * 1e-3) / 1e9
     cols_b, rows_b = kernel_bytes(N5, P5)
-    rname = "k_rows<512,%d,%d,0,%s>" % (pd.variants(N5, 0)[rv][0], abs(pd.variants(N5, 0)[rv][1]),
-                                        "true" if pd.variants(N5, 0)[rv][1] < 0 else "false")
+    re_, rw_ = pd.variants(N5, 0)[rv]
+    rname = ("k_rows_c3<512,%d>" % re_ if rw_ == 3 else
+             "k_rows<512,%d,%d,0,%s>" % (re_, abs(rw_), "true" if rw_ < 0 else "false"))
     ce, ctx_ = pd.variants(N5, 1)[cv]
     cname = ("k_cols<512,%d,%d>" % (ce, ctx_) if ctx_ > 0 else "k_cols_pf<512,%d,%d>" % (ce, -ctx_))
     tr_c = measured_traffic("pd::" + cname, TRAFFIC_FILE5)

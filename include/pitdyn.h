@@ -269,7 +269,7 @@ pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate);
    state, history and row buffers stay in the device's last-level cache
    across its steps instead of streaming through HBM at every step.
    group = 0: off (every step runs over the whole batch); group = -1
-   (default): groups of 2 fields on 3 streams at 512^2, of 16 fields on 2
+   (default): groups of 3 fields on 3 streams at 512^2, of 16 fields on 2
    streams at 256^2, off on smaller grids.  Applies to the multi-launch path (fine sweeps of pd_parareal,
    pd_fine_dev / pd_steps_dev batches, pd_fine_sweep_steps, pd_profile_fine);
    in the pipelined schedule each run of slices is blocked on its own fine
@@ -346,8 +346,9 @@ pd_status pd_autotune(pd_ctx* ctx, int reps, const char* cache_path, int* chosen
 /* Variant table: v = -1 puts the number of variants of `kind` (0 rows,
    1 columns) for grid N in *a; v >= 0 describes variant v (rows: *a values a
    lane, *b waves a workgroup, negative for the form that loads a row's state
-   and history with the row; columns: *a values a lane, *b columns a
-   workgroup). */
+   and history with the row, 3 for the form with one row a workgroup and its
+   three components on three waves; columns: *a values a lane, *b columns a
+   workgroup, negative for the persistent form). */
 pd_status pd_variant_info(int N, int kind, int v, int* a, int* b);
 /* Select the process-wide default launch-shape variants for grid N (0, 0 =
    defaults), used by contexts and batches that were not autotuned. */

@@ -367,6 +367,99 @@ __global__ __launch_bounds__(64 * W) void k_rows(FieldBatchT<C> fb, Problem pb, 
                        RKS > 0 ? fb.R + 4 * f * box : nullptr);
 }
 
+// Row phase with the three components of one box row on three wavefronts of
+// one workgroup (wavefront c transforms component c, T = 64 lanes), so a lane
+// holds one component's E values instead of three, and a SIMD holds several
+// waves where the one-row kernel above fits one (N = 512).  The spectral curl
+// needs all three components of a mode: after its forward transform each
+// wave leaves its (unscaled) spectrum in its own LDS span, a barrier, then
+// each wave reads the other two components of its lanes' modes and updates
+// its own component; a second barrier keeps the spans until every wave has
+// read them, before the inverse transforms reuse them.  SBDF modes 0, 1, 2
+// only; per mode the same operations as row_phase in the same order.
+template <int N, int E, class C = cplx>
+__global__ __launch_bounds__(3 * (N / E)) void k_rows_c3(FieldBatchT<C> fb, Problem pb, int mode,
+                                                         int last) {
+  using G = Geo<N, E>;
+  using Rl = decltype(C::re);
+  constexpr int T = G::T, K = G::K, M = G::M, SP = G::SPAN;
+  static_assert(T == 64, "one wavefront per component");
+  __shared__ C sm[3 * SP];
+  if (fb.count != nullptr && (int)blockIdx.y >= *fb.count) return;
+  const int c = threadIdx.x / T, j = threadIdx.x % T;
+  const int r = blockIdx.x;  // one box row a workgroup: the grid is exactly M wide
+  const size_t f = fb.map != nullptr ? (size_t)fb.map[blockIdx.y] : (size_t)blockIdx.y;
+  const size_t box = (size_t)3 * M * M, rows = (size_t)3 * M * N;
+  C* __restrict__ B = fb.B + f * box;
+  C* __restrict__ H = fb.H + f * box;
+  C* __restrict__ T1 = fb.T1 + f * rows;
+  const C* __restrict__ T2 = fb.T2 + f * rows;
+  const Rl Rm = (Rl)(fb.fRm != nullptr ? fb.fRm[f] : pb.Rm);
+  const Rl kz = (Rl)(fb.fkz != nullptr ? fb.fkz[f] : pb.kz);
+  C* s = sm + c * SP;
+  TwRegs<N, E, C> twr;
+  twr.load(j, fb.tw);
+  C w[E];
+  const int ky = r - K;
+  if (mode == 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = signed_k(j + T * e, N);
+      w[e] = (kx >= -K && kx <= K) ? B[(c * M + r) * M + kx + K] : zero_of<C>();
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[e] = T2[(c * M + r) * N + j + T * e];
+    fft<N, E, -1>(w, s, j, twr);
+#pragma unroll
+    for (int e = 0; e < E; ++e) s[j + T * e] = w[e];
+    __syncthreads();
+    const C* s1 = sm + ((c + 1) % 3) * SP;  // the next and the one after (cyclic)
+    const C* s2 = sm + ((c + 2) % 3) * SP;
+    const Rl sc = (Rl)(1.0 / ((double)N * (double)N));
+    const Rl dt = (Rl)pb.dt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = signed_k(j + T * e, N);
+      if (kx >= -K && kx <= K) {
+        // the curl's component c does not involve E_c itself
+        const C o1 = cscale(s1[j + T * e], sc), o2 = cscale(s2[j + T * e], sc);
+        const Rl dkx = kx, dky = ky;
+        // i k x E, component c only (x: c = 0, y: 1, z: 2)
+        C nl;
+        if (c == 0)  // (ey, ez) = (o1, o2)
+          nl = mul_i<1>(csub(cscale(o2, dky), cscale(o1, kz)));
+        else if (c == 1)  // (ez, ex) = (o1, o2)
+          nl = mul_i<1>(csub(cscale(o2, kz), cscale(o1, dkx)));
+        else  // (ex, ey) = (o1, o2)
+          nl = mul_i<1>(csub(cscale(o2, dkx), cscale(o1, dky)));
+        const Rl a = dt * (dkx * dkx + dky * dky + kz * kz) / Rm;
+        const int idx = (c * M + r) * M + kx + K;
+        const C b = B[idx];
+        C bn;
+        if (mode == 1) {
+          const Rl inv = (Rl)1 / ((Rl)1 + a);
+          bn = cscale(cadd(b, cscale(nl, dt)), inv);
+        } else {
+          const Rl inv = (Rl)1 / ((Rl)1.5 + a);
+          bn = cscale(cadd(cadd(cscale(b, (Rl)2), cscale(nl, (Rl)2 * dt)), H[idx]), inv);
+        }
+        H[idx] = csub(cscale(b, (Rl)-0.5), cscale(nl, dt));
+        B[idx] = bn;
+        w[e] = bn;
+      } else {
+        w[e] = zero_of<C>();
+      }
+    }
+    __syncthreads();
+  }
+  if (!last) {
+    fft<N, E, 1>(w, s, j, twr);
+#pragma unroll
+    for (int e = 0; e < E; ++e) T1[(c * M + r) * N + j + T * e] = w[e];
+  }
+}
+
 // Workgroups are handed to the eight XCDs round-robin by linear block index.
 // When a column tile is narrower than a 128-byte line (TX < 8), the GL
 // workgroups whose tiles share lines are given block indices b, b + 8, ...,
@@ -1189,6 +1282,17 @@ static hipError_t launch_rows_v(const FieldBatch& fb, const Problem& pb, int nfi
   return hipGetLastError();
 }
 
+// The component-split row kernel for the SBDF modes; the Runge-Kutta stage
+// modes run the one-row kernel.
+template <int N, int E>
+static hipError_t launch_rows_c3(const FieldBatch& fb, const Problem& pb, int nfields, int mode,
+                                 int last, hipStream_t st) {
+  if (mode >= ROW_RK) return launch_rows_v<N, E, 1>(fb, pb, nfields, mode, last, st);
+  hipLaunchKernelGGL((k_rows_c3<N, E>), dim3(Geo<N, E>::M, nfields), dim3(3 * Geo<N, E>::T), 0, st,
+                     fb, pb, mode, last);
+  return hipGetLastError();
+}
+
 template <int N, int E, int TX, int MINW>
 static hipError_t launch_cols_v(const FieldBatch& fb, const Problem& pb, int nfields, int step,
                                 int stage, hipStream_t st) {
@@ -1242,7 +1346,8 @@ struct ColsVariant {
 
 // Candidates: rows -- values a lane E (8 or 4), waves a workgroup W, W < 0 for
 // the form that loads the state and history with the row (faster on small
-// batches, fewer waves); columns -- values a lane E, columns a workgroup TX
+// batches, fewer waves), W = 3 for the component-split form (one row a
+// workgroup, one component a wave; the default at 512); columns -- values a lane E, columns a workgroup TX
 // (lanes <= 1024, LDS <= 160 KB), TX < 0 for the persistent form with |TX|
 // columns a tile.
 template <int N>
@@ -1293,7 +1398,8 @@ struct Variants<256> {
   static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<256, 8, 1>},
                                          {8, 2, launch_rows_v<256, 8, 2>},
                                          {4, 1, launch_rows_v<256, 4, 1>},
-                                         {4, -1, launch_rows_v<256, 4, 1, true>}};
+                                         {4, -1, launch_rows_v<256, 4, 1, true>},
+                                         {4, 3, launch_rows_c3<256, 4>}};
   static constexpr ColsVariant cols[] = {{4, 16, launch_cols_v<256, 4, 16, 4>},
                                          {4, 8, launch_cols_v<256, 4, 8, 4>},
                                          {8, 16, launch_cols_v<256, 8, 16, 2>},
@@ -1303,7 +1409,8 @@ struct Variants<256> {
 };
 template <>
 struct Variants<512> {
-  static constexpr RowsVariant rows[] = {{8, 1, launch_rows_v<512, 8, 1>},
+  static constexpr RowsVariant rows[] = {{8, 3, launch_rows_c3<512, 8>},
+                                         {8, 1, launch_rows_v<512, 8, 1>},
                                          {8, 2, launch_rows_v<512, 8, 2>}};
   static constexpr ColsVariant cols[] = {{8, 8, launch_cols_v<512, 8, 8, 2>},
                                          {8, 4, launch_cols_v<512, 8, 4, 2>},

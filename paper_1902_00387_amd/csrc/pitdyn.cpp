@@ -144,14 +144,14 @@ int choose_path(const pd_ctx* c, int nfields) {
 // 256 MB memory-side last-level cache from one step to the next, and the
 // phases of groups on different streams overlap.  Defaults measured on
 // MI355X (K steps of every slice, best launch shapes): 512^2 x 256 fields,
-// groups of 2 on 3 streams, 2.74 against 3.46 ms a step unblocked; 256^2 x
-// 128, groups of 16 on 2 streams, 0.353 against 0.405 ms; 128^2 x 64 gains
-// under 10 % (its whole batch, about 200 MB, already fits the cache) and
-// stays unblocked.
+// groups of 3 on 3 streams, 2.51-2.66 against 3.24 ms a step unblocked;
+// 256^2 x 128, groups of 16 on 2 streams, 0.353 against 0.405 ms; 128^2 x 64
+// gains under 10 % (its whole batch, about 200 MB, already fits the cache)
+// and stays unblocked.
 void fine_blocking(const pd_ctx* c, int nfields, int* group, int* streams) {
   int g = c->blk_g, s = c->blk_s;
   if (g < 0) {
-    g = c->N >= 512 ? 2 : c->N == 256 ? 16 : 0;
+    g = c->N >= 512 ? 3 : c->N == 256 ? 16 : 0;
     s = c->N >= 512 ? 3 : 2;
   }
   if (g >= nfields) g = 0;

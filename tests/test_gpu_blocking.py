@@ -100,7 +100,7 @@ def test_default_blocking_and_argument_errors(lib):
         with pytest.raises(lib.PitdynError):
             ctx.fine_blocking()                   # before pd_set_time
         ctx.set_time(4.0, 4, 5e-4, 2.5e-3, 64)
-        assert ctx.fine_blocking() == (2, 3)      # default at 512^2
+        assert ctx.fine_blocking() == (3, 3)      # default at 512^2
         ctx.set_fine_blocking(0)
         assert ctx.fine_blocking() == OFF
         ctx.set_fine_blocking(4, 2)
