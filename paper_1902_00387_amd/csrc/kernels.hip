@@ -1412,8 +1412,8 @@ struct Variants<512> {
   static constexpr RowsVariant rows[] = {{8, 3, launch_rows_c3<512, 8>},
                                          {8, 1, launch_rows_v<512, 8, 1>},
                                          {8, 2, launch_rows_v<512, 8, 2>}};
-  static constexpr ColsVariant cols[] = {{8, 8, launch_cols_v<512, 8, 8, 2>},
-                                         {8, 4, launch_cols_v<512, 8, 4, 2>},
+  static constexpr ColsVariant cols[] = {{8, 4, launch_cols_v<512, 8, 4, 2>},
+                                         {8, 8, launch_cols_v<512, 8, 8, 2>},
                                          {8, -4, launch_cols_pf<512, 8, 4>}};
 };
 
