@@ -11,10 +11,10 @@ it (column phase: inverse y-FFT, u x b, forward y-FFT with the 2/3 mask; row
 phase: forward x-FFT, 1/N^2, spectral curl, implicit diffusion solve, SBDF
 update, inverse x-FFT): 512^2 x 256 = 67.1 M mode-steps.
 
-The sweep runs as Parareal runs it: at 512^2 the library blocks it in time,
-groups of 3 slices running all their steps back to back on 3 streams, so a
-group's buffers stay in the memory-side last-level cache between steps; the
-K timed steps are K steps of every slice.
+The sweep runs as Parareal runs it: blocked in time as the autotuner chooses
+(at 512^2 groups of 2-3 slices running all their steps back to back on 3
+streams), so a group's buffers stay in the memory-side last-level cache
+between steps; the K timed steps are K steps of every slice.
 
 value: fine-propagator mode-steps per second, N^2 * slices * K / (time of K
   steps); the states are resident in HBM before the timed region.
@@ -139,12 +139,14 @@ def summarize_trace(trace_csv, steps, fields):
         n = r["Kernel_Name"].split("(")[0]
         return n[5:] if n.startswith("void ") else n
     ks = [r for r in rows if kname(r).startswith(("pd::k_cols", "pd::k_rows"))]
-    # the sweep's launches are those over a group: the most frequent grid
-    # height below the whole batch (not the whole-batch start, the autotuner's
-    # launches or a persistent kernel's one-row grid)
+    # the sweep's launches are the group launches after its start, the last
+    # whole-batch launch of the program (the inverse-only row launch of step
+    # 0; the autotuner's launches, whole-batch and grouped, come before it)
+    ks.sort(key=lambda r: int(r["Start_Timestamp"]))
+    last_full = max(i for i, r in enumerate(ks) if int(r["Grid_Size_Y"]) == int(fields))
+    ks = ks[last_full + 1:]
     from collections import Counter
-    ys = Counter(int(r["Grid_Size_Y"]) for r in ks if 1 < int(r["Grid_Size_Y"]) < int(fields))
-    gy = ys.most_common(1)[0][0]
+    gy = Counter(int(r["Grid_Size_Y"]) for r in ks).most_common(1)[0][0]
     ks = [r for r in ks if int(r["Grid_Size_Y"]) == gy]
     out = {"dispatches": len(ks), "kernels": {}}
     for r in ks:
@@ -171,9 +173,17 @@ def summarize_pmc(fetch_csv, write_csv, out_path):
     import statistics
 
     def per_kernel(path):
+        # dispatches over the whole batch only (the largest grid of each
+        # kernel): the autotuner's blocked-sweep candidates launch the same
+        # kernels over groups of a few fields
+        rows = list(csv.DictReader(open(path)))
+        big = {}
+        for r in rows:
+            big[r["Kernel_Name"]] = max(big.get(r["Kernel_Name"], 0), int(r["Grid_Size"]))
         acc = {}
-        for r in csv.DictReader(open(path)):
-            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        for r in rows:
+            if "copyBuffer" in r["Kernel_Name"] or int(r["Grid_Size"]) == big[r["Kernel_Name"]]:
+                acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return acc
     fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
     copy_bytes = float(1 << 30)
@@ -801,6 +811,10 @@ def run_config2(args):
             # eq. speed_up from the report's per-stream sweep times (they
             # overlap in the pipelined schedule, so R_f and R_c are overstated)
             "Rf_over_Rc": rep["Rf_over_Rc"], "model_speedup": rep["model_speedup"],
+            "model_speedup_note": "eq. speed_up with R_f / R_c from the report's summed fine and "
+                                  "coarse kernel times per stream; in the pipelined schedule the "
+                                  "sweeps overlap, so this overstates the measured speed-up "
+                                  "(speedup_vs_serial_fine_gpu)",
         },
         "autotune": {"rows_variant": list(pd.variants(N, 0)[tuned[0]]),
                      "cols_variant": list(pd.variants(N, 1)[tuned[1]]),
@@ -874,9 +888,9 @@ def run_headline(args, cpu):
     ctx.fine_sweep_steps(0, 1)
     mk = ctx.fine_sweep_steps(1, KS, timed=True)
     ms_cols, ms_rows = mk[0] / KS, mk[1] / KS
-    # the sweep as Parareal runs it (blocked in groups of fields when the
-    # library's default says so), continued from there
-    ctx.set_fine_blocking(-1)
+    # the sweep as Parareal runs it (blocked in groups of fields as the
+    # autotuner chose), continued from there
+    ctx.set_fine_blocking(group, nstreams)
     s0 = 1 + KS
     if args.warmup > 0:
         for a, c in _sweep_chunks(s0, args.warmup, nf):
@@ -1024,7 +1038,7 @@ def run_kernel_only5(args):
     nf = int(round(T5 / P5 / DT5))
     ctx, _ = headline_context(pd)
     if args.blocked_only:
-        ctx.set_fine_blocking(-1)
+        pass  # the autotuner's blocking, as the benchmark times it
     else:
         # whole-batch launches: one dispatch per kernel and step
         ctx.set_fine_blocking(0)

@@ -336,11 +336,15 @@ pd_status pd_get_fine_states_dev(const pd_ctx* ctx, int first, int count, void* 
    inputs are the current slice states, which are left unchanged), selects the
    fastest of each for this context, and returns their indices in
    chosen[0] (rows), chosen[1] (columns) and their mean launch times in ms[0..1]
-   (either may be NULL).  The choice belongs to this context (it applies to
+   (either may be NULL).  With those shapes it then times the fine sweep
+   (12 steps of every slice) whole-batch and in the blocked orders of
+   pd_set_fine_blocking (groups of 1 to 32 fields on 2 or 3 streams) and keeps
+   the fastest as this context's blocking (pd_get_fine_blocking; a later
+   pd_set_fine_blocking overrides it).  The choice belongs to this context (it applies to
    its fine propagator calls, sweeps and pd_parareal until the next
    pd_set_problem); other contexts keep theirs.  With cache_path non-NULL the choice is first looked
-   up in that JSON file (key "<gfx arch>|<N>|<n_slices>"; ms = 0 on a hit) and
-   stored there after timing.  Variants give identical results bitwise only
+   up in that JSON file (key "<gfx arch>|<N>|<n_slices>", value [rows, cols,
+   group, streams]; ms = 0 on a hit) and stored there after timing.  Variants give identical results bitwise only
    with equal values a lane; all agree with the oracle to the parity bar. */
 pd_status pd_autotune(pd_ctx* ctx, int reps, const char* cache_path, int* chosen, double* ms);
 /* Variant table: v = -1 puts the number of variants of `kind` (0 rows,

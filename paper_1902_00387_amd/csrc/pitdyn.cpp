@@ -990,9 +990,17 @@ std::string tune_key(int device, int N, int P) {
 }
 
 // The cache is a flat JSON object {"<arch>|<N>|<batch>": [rows, cols], ...}.
-bool cache_lookup(const char* path, const std::string& key, int* rv, int* cv) {
+// Cache entries hold [rows, cols] or [rows, cols, group, streams] (the
+// fine-sweep blocking); v receives up to four values, the count is returned
+// (0: no entry).
+int parse_entry(const char* p, int v[4]) {
+  const int n = std::sscanf(p, " : [ %d , %d , %d , %d ]", &v[0], &v[1], &v[2], &v[3]);
+  return n >= 2 ? n : 0;
+}
+
+int cache_lookup(const char* path, const std::string& key, int v[4]) {
   FILE* f = std::fopen(path, "r");
-  if (!f) return false;
+  if (!f) return 0;
   std::string text;
   char buf[4096];
   size_t n;
@@ -1000,12 +1008,17 @@ bool cache_lookup(const char* path, const std::string& key, int* rv, int* cv) {
   std::fclose(f);
   const std::string q = "\"" + key + "\"";
   const size_t at = text.find(q);
-  if (at == std::string::npos) return false;
-  return std::sscanf(text.c_str() + at + q.size(), " : [ %d , %d ]", rv, cv) == 2;
+  if (at == std::string::npos) return 0;
+  return parse_entry(text.c_str() + at + q.size(), v);
 }
 
-void cache_store(const char* path, const std::string& key, int rv, int cv) {
-  std::vector<std::pair<std::string, std::pair<int, int>>> entries;
+void cache_store(const char* path, const std::string& key, const int val[4]) {
+  struct Entry {
+    std::string k;
+    int v[4];
+    int n;
+  };
+  std::vector<Entry> entries;
   FILE* f = std::fopen(path, "r");
   if (f) {
     std::string text;
@@ -1017,20 +1030,26 @@ void cache_store(const char* path, const std::string& key, int rv, int cv) {
     while ((pos = text.find('"', pos)) != std::string::npos) {
       const size_t end = text.find('"', pos + 1);
       if (end == std::string::npos) break;
-      const std::string k = text.substr(pos + 1, end - pos - 1);
-      int a = 0, b = 0;
-      if (std::sscanf(text.c_str() + end + 1, " : [ %d , %d ]", &a, &b) == 2 && k != key)
-        entries.push_back({k, {a, b}});
+      Entry e;
+      e.k = text.substr(pos + 1, end - pos - 1);
+      e.n = parse_entry(text.c_str() + end + 1, e.v);
+      if (e.n > 0 && e.k != key) entries.push_back(e);
       pos = end + 1;
     }
   }
-  entries.push_back({key, {rv, cv}});
+  Entry mine;
+  mine.k = key;
+  mine.n = 4;
+  for (int i = 0; i < 4; ++i) mine.v[i] = val[i];
+  entries.push_back(mine);
   f = std::fopen(path, "w");
   if (!f) return;
   std::fprintf(f, "{\n");
-  for (size_t i = 0; i < entries.size(); ++i)
-    std::fprintf(f, "  \"%s\": [%d, %d]%s\n", entries[i].first.c_str(), entries[i].second.first,
-                 entries[i].second.second, i + 1 < entries.size() ? "," : "");
+  for (size_t i = 0; i < entries.size(); ++i) {
+    std::fprintf(f, "  \"%s\": [", entries[i].k.c_str());
+    for (int j = 0; j < entries[i].n; ++j) std::fprintf(f, "%s%d", j ? ", " : "", entries[i].v[j]);
+    std::fprintf(f, "]%s\n", i + 1 < entries.size() ? "," : "");
+  }
   std::fprintf(f, "}\n");
   std::fclose(f);
 }
@@ -1063,11 +1082,17 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   DeviceGuard dg(c->device);
   const int P = c->P;
   const std::string key = tune_key(c->device, c->N, P);
-  int rv = 0, cv = 0;
-  if (cache_path && cache_lookup(cache_path, key, &rv, &cv) && rv >= 0 &&
-      rv < pd::variant_count(c->N, 0) && cv >= 0 && cv < pd::variant_count(c->N, 1)) {
+  int cv4[4] = {0, 0, -1, 0};
+  const int cn = cache_path ? cache_lookup(cache_path, key, cv4) : 0;
+  const int rv = cv4[0], cv = cv4[1];
+  if (cn >= 2 && rv >= 0 && rv < pd::variant_count(c->N, 0) && cv >= 0 &&
+      cv < pd::variant_count(c->N, 1)) {
     c->rows_v = rv;
     c->cols_v = cv;
+    if (cn == 4 && cv4[2] >= 0 && (cv4[2] == 0 || (cv4[3] >= 1 && cv4[3] <= 3))) {
+      c->blk_g = cv4[2];
+      c->blk_s = cv4[2] > 0 ? cv4[3] : 0;
+    }
     if (chosen) {
       chosen[0] = rv;
       chosen[1] = cv;
@@ -1145,7 +1170,51 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
     ms[0] = best[0] / reps;
     ms[1] = best[1] / reps;
   }
-  if (cache_path) cache_store(cache_path, key, bestv[0], bestv[1]);
+  // the fine sweep's blocking (groups of fields that run all their steps back
+  // to back, dealt to streams): each candidate runs BLK_STEPS steps of every
+  // field in its order with the chosen launch shapes
+  {
+    constexpr int BLK_STEPS = 12;
+    static const int cand[][2] = {{0, 1}, {1, 3}, {2, 3}, {3, 3}, {4, 3}, {8, 3}, {16, 3},
+                                  {2, 2}, {4, 2}, {8, 2}, {16, 2}, {32, 2}};
+    pd::FieldBatch q = fb;
+    q.rows_v = c->rows_v;
+    q.cols_v = c->cols_v;
+    auto steps = [&](const pd::FieldBatch& x, int ng, hipStream_t s) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int k = 1; k <= BLK_STEPS && e == hipSuccess; ++k) {
+        e = pd::cols(c->N, x, pf, ng, k, s);
+        if (e == hipSuccess) e = pd::rows(c->N, x, pf, ng, 2, 0, s);
+      }
+      return e;
+    };
+    auto sweep = [&](int g, int ns) -> hipError_t {
+      return g == 0 ? steps(q, P, st) : over_groups(c, q, P, g, ns, st, steps);
+    };
+    PD_HIP(c, sweep(0, 1), "autotune");  // warm-up
+    float bt = 1e30f;
+    int bg = 0, bs = 1;
+    for (const auto& cd : cand) {
+      if (cd[0] >= P) continue;
+      float t = 0;
+      PD_HIP(c, hipEventRecord(ev[0], st), "event");
+      PD_HIP(c, sweep(cd[0], cd[1]), "autotune");
+      PD_HIP(c, hipEventRecord(ev[1], st), "event");
+      PD_HIP(c, hipEventSynchronize(ev[1]), "sync");
+      PD_HIP(c, hipEventElapsedTime(&t, ev[0], ev[1]), "event");
+      if (t < bt) {
+        bt = t;
+        bg = cd[0];
+        bs = cd[1];
+      }
+    }
+    c->blk_g = bg;
+    c->blk_s = bg > 0 ? bs : 0;
+  }
+  if (cache_path) {
+    const int val[4] = {bestv[0], bestv[1], c->blk_g, c->blk_g > 0 ? c->blk_s : 1};
+    cache_store(cache_path, key, val);
+  }
   return PD_OK;
 }
 

@@ -306,8 +306,12 @@ def test_autotune_selects_and_caches(ctx, lib, tmp_path):
         assert mr > 0 and mc > 0
         text = open(cache).read()
         assert f"|{N}|8" in text
+        blk = ctx.fine_blocking()                       # tuned with the launch shapes
+        assert blk[0] in (0, 1, 2, 3, 4) and 1 <= blk[1] <= 3
+        ctx.set_fine_blocking(-1)
         (rv2, cv2), (mr2, mc2) = ctx.autotune(5, cache)   # cache hit
         assert (rv2, cv2) == (rv, cv) and mr2 == 0.0
+        assert ctx.fine_blocking() == blk               # the cached blocking
         # Parareal after tuning still matches an untuned context (the choice
         # is this context's; another context keeps the defaults) to the bar
         ctx.set_initial(initial_field(N, 0.57, 5))
