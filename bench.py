@@ -458,6 +458,134 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def _solve_in_pieces(ctx, tol, cap, piece, label):
+    """Parareal to sigma <= tol (at most `cap` iterations) in pieces of
+    `piece` iterations (pd_parareal, then pd_parareal_continue), one progress
+    line a piece; returns (report of the last piece, sigma of every
+    iteration, seconds)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = ctx.parareal(tol, min(piece, cap))
+    sig = list(rep["sigma"])
+    _log(f"# {label}: iteration {rep['iters']}, sigma {sig[-1]:.3e}, {time.perf_counter() - t0:.1f} s")
+    while rep["k_con"] < 0 and rep["iters"] < cap:
+        rep = ctx.parareal_continue(tol, min(rep["iters"] + piece, cap))
+        sig += rep["sigma"][len(sig):]
+        _log(f"# {label}: iteration {rep['iters']}, sigma {sig[-1]:.3e}, "
+             f"{time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    return rep, sig, time.perf_counter() - t0
+
+
+def run_learned5(args):
+    """Learned against plain coarse propagator on the 512^2, 256-slice
+    workload (Rm = 2000): time and iterations to sigma <= tol, each solve run
+    in pieces of a few iterations; the network (BF16 matrix-core operands) is
+    trained on the GPU on the coarse-propagator inputs of iterations k >= K0
+    of a plain-G run from another seeded field."""
+    import torch
+
+    import paper_1902_00387_amd as pd
+    nc, dtc, cap, tol = args.p5_nc, args.p5_dtc, args.l5_iters, args.l5_tol
+    piece = 4
+    ctx = pd.Context(0)
+    ctx.set_problem("gp", RM5, KZ, N5)
+    ctx.set_time(T5, P5, DT5, dtc, nc)
+    ctx.seed_initial(SEED5, 1e-3, 4.0)
+    ctx.parareal(0.0, 0)
+    ctx.autotune(3)
+    _log(f"# blocking {ctx.fine_blocking()}")
+    b0 = ctx.get_slices_dev()[0:1].clone()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    u = b0
+    for n in range(P5):
+        u = ctx.fine([n * T5 / P5], u)
+        if n % 128 == 127:
+            _log(f"# serial fine: slice {n + 1}/{P5}, {time.perf_counter() - ts:.1f} s")
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - ts
+    del u
+
+    def solve(learned):
+        ctx.set_coarse(False)
+        ctx.seed_initial(SEED5, 1e-3, 4.0)
+        if learned and args.l5_switch > 0:
+            # plain G for the first iterations, then the learned propagator
+            # (trained on the differences of later iterations)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r0 = ctx.parareal(tol, args.l5_switch)
+            sig0 = list(r0["sigma"])
+            ctx.set_coarse(True)
+            rep = r0
+            sig = sig0
+            while rep["k_con"] < 0 and rep["iters"] < cap:
+                rep = ctx.parareal_continue(tol, min(rep["iters"] + piece, cap))
+                sig += rep["sigma"][len(sig):]
+                _log(f"# plain then learned G: iteration {rep['iters']}, sigma {sig[-1]:.3e}, "
+                     f"{time.perf_counter() - t0:.1f} s")
+            torch.cuda.synchronize()
+            return rep, sig, time.perf_counter() - t0, ctx.growth_rate()
+        ctx.set_coarse(learned)
+        rep, sig, secs = _solve_in_pieces(ctx, tol, cap, piece, "learned G" if learned else "plain G")
+        return rep, sig, secs, ctx.growth_rate()
+
+    rp, sp, tp, gp = solve(False)
+    Up = ctx.get_slices_dev()[P5].clone()
+    # training pairs: the coarse inputs U^k_n - U^{k-1}_n of a plain-G run
+    # from another seeded field, iterations k >= K0 (the error that persists)
+    H, K0, steps = args.l5_harvest, args.lg_late, args.l5_steps
+    ctx.lg_init(4, SEED5)
+    tg = time.perf_counter()
+    ctx.set_coarse(False)
+    ctx.seed_initial(SEED5 + 1000, 1e-3, 4.0)
+    n_samples = ctx.lg_add_parareal_samples(H)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - tg
+    _log(f"# {n_samples} training pairs in {gen_s:.1f} s")
+    skip = P5 + (K0 - 1) * P5 - (K0 - 1) * K0 // 2
+    va_n = 64
+    tr0, trn = skip, n_samples - skip - va_n
+    va0 = n_samples - va_n
+    val0 = ctx.lg_loss(va0, va_n)
+    ttr = time.perf_counter()
+    done = 0
+    last = float("nan")
+    while done < steps:
+        k = min(250, steps - done)
+        losses = ctx.lg_train(tr0, trn, k, 8, 1e-3, seed=5 + done)
+        done += k
+        last = float(losses[-1])
+        _log(f"# training: {done}/{steps} steps, batch loss {last:.3f}, "
+             f"{time.perf_counter() - ttr:.1f} s")
+    val1 = ctx.lg_loss(va0, va_n)
+    train_s = time.perf_counter() - ttr
+    _log(f"# held-out loss {val0:.3f} -> {val1:.3f}")
+    rl, sl, tl, gl = solve(True)
+    Ul = ctx.get_slices_dev()[P5]
+    diff = float(torch.linalg.vector_norm(Ul - Up).item() / torch.linalg.vector_norm(Up).item())
+    ctx.close()
+    out = {
+        "experiment": "learned vs plain coarse propagator on the 512^2, 256-slice workload",
+        "config": {"workload": "Galloway-Proctor Rm=2000, kz=0.57, 512x512, T=256 over 256 slices, "
+                               f"fine SBDF2 dt=5e-4, coarse SBDF2 on {nc}^2 dt={dtc}, tol {tol:g}, "
+                               "network 4 layers width 32 (BF16 operands)"},
+        "plain": {"k_con": rp["k_con"], "iters": rp["iters"], "time_s": tp, "growth_rate": gp,
+                  "sigma": sp},
+        "learned": {"k_con": rl["k_con"], "iters": rl["iters"], "time_s": tl, "growth_rate": gl,
+                    "plain_iterations_first": args.l5_switch,
+                    "sigma": sl, "final_state_reldiff_vs_plain": diff},
+        "serial_fine_gpu_s": serial_s,
+        "training": {"pairs": n_samples, "harvest_iterations": H, "trained_on": [tr0, trn],
+                     "held_out": [va0, va_n], "generate_s": gen_s, "train_s": train_s,
+                     "steps": steps, "batch": 8, "held_out_loss": [val0, val1],
+                     "last_batch_loss": last},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -1183,6 +1311,14 @@ def main():
     ap.add_argument("--p5-iters", type=int, default=8, help="--parareal5: iteration cap")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the fine-sweep kernels (for profiler runs)")
+    ap.add_argument("--learned5", action="store_true",
+                    help="learned vs plain coarse propagator on the 512^2 workload")
+    ap.add_argument("--l5-tol", type=float, default=1e-8, help="--learned5: defect tolerance")
+    ap.add_argument("--l5-iters", type=int, default=40, help="--learned5: iteration cap")
+    ap.add_argument("--l5-harvest", type=int, default=8, help="--learned5: harvested iterations")
+    ap.add_argument("--l5-steps", type=int, default=2000, help="--learned5: Adam steps")
+    ap.add_argument("--l5-switch", type=int, default=0,
+                    help="--learned5: plain G for this many iterations, then the learned one")
     ap.add_argument("--blocking-sweep", action="store_true",
                     help="time the fine sweep for fine-blocking settings and launch shapes")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_CSV", "STEPS", "FIELDS"),
@@ -1228,7 +1364,7 @@ def main():
 
     default = not (args.batch or args.learned or args.nc_sweep or args.nc_sweep_gp or
                    args.work_precision or args.table1 or args.config2 or args.parareal5 or
-                   args.kernel_only or args.c64 or args.blocking_sweep)
+                   args.kernel_only or args.c64 or args.blocking_sweep or args.learned5)
     if args.steps is None:
         args.steps = 1 if args.batch else 20 if args.config2 or args.kernel_only else 100
     if args.warmup is None:
@@ -1267,6 +1403,9 @@ def main():
         return
     if args.blocking_sweep:
         run_blocking_sweep(args)
+        return
+    if args.learned5:
+        run_learned5(args)
         return
     run_headline(args, cpu)
 

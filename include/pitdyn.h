@@ -242,6 +242,21 @@ pd_status pd_steps_dev_noalloc(pd_ctx* ctx, const double* t0, int batch, double 
    results are unchanged bitwise.  `rep` may be NULL.  Returns PD_OK,
    PD_NOT_CONVERGED, or PD_EUNSTABLE if a defect sum is not finite. */
 pd_status pd_parareal(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
+/* Continue the last pd_parareal (or pd_parareal_continue) of this context
+   after the k iterations it completed, from the state it left on the device
+   (U^k and, for the plain coarse propagator, G(U^k_n)), as pd_set_slices
+   would with that state and k, but without copies: iterations k+1 ..
+   max_iter (absolute; max_iter > k) until sigma <= tol.  The iterates, the
+   defects and k_con are bitwise those of one uninterrupted call; rep numbers
+   iterations absolutely and times only this call.  Lets a long solve run in
+   bounded pieces.  PD_ESTATE when there is nothing to continue: no run yet,
+   or one of pd_set_problem, pd_set_time, pd_set_precision, pd_set_initial,
+   pd_set_slices, pd_set_scheme, pd_set_coarse from the learned to the plain
+   propagator, pd_lg_add_parareal_samples since, or the last run ended in
+   PD_EUNSTABLE.  Switching from the plain to the learned propagator between
+   calls is allowed (its difference form needs only U^k): iterations up to k
+   with G, the following ones with the learned one. */
+pd_status pd_parareal_continue(pd_ctx* ctx, double tol, int max_iter, pd_report* rep);
 
 /* Order of the work inside pd_parareal with the plain coarse propagator.
    chunks >= 2 (default 2, speculate 2): pipelined -- the serial coarse sweep runs on a stream of its

@@ -63,6 +63,7 @@ SYMBOLS = [
     "pd_seed_field", "pd_seed_initial", "pd_fine_sweep_steps",
     "pd_get_fine_states_dev", "pd_steps_dev_noalloc", "pd_lg_add_feature_samples",
     "pd_lg_set_operands", "pd_set_precision", "pd_set_fine_blocking", "pd_get_fine_blocking",
+    "pd_parareal_continue",
 ]
 
 
@@ -165,6 +166,7 @@ def _load():
         "pd_set_precision": ([vp, i], i),
         "pd_set_fine_blocking": ([vp, i, i], i),
         "pd_get_fine_blocking": ([vp, C.POINTER(i), C.POINTER(i)], i),
+        "pd_parareal_continue": ([vp, d, i, C.POINTER(Report)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -304,6 +306,16 @@ class Context:
     def parareal(self, tol: float, max_iter: int):
         rep = Report()
         st = self._ok(lib.pd_parareal(self._h, float(tol), int(max_iter), C.byref(rep)),
+                      allow=(OK, NOT_CONVERGED))
+        d = rep.as_dict()
+        d["status"] = st
+        return d
+
+    def parareal_continue(self, tol: float, max_iter: int):
+        """Continue the last parareal() after the iterations it completed, up
+        to iteration max_iter (absolute)."""
+        rep = Report()
+        st = self._ok(lib.pd_parareal_continue(self._h, float(tol), int(max_iter), C.byref(rep)),
                       allow=(OK, NOT_CONVERGED))
         d = rep.as_dict()
         d["status"] = st

@@ -47,6 +47,8 @@ struct pd_ctx {
   int P = 0, Nc = 0, Mc = 0, nf = 0, nc = 0;
   bool have_initial = false;
   int resume_k = -1;                   // pd_set_slices: the next pd_parareal goes on after iteration k
+  int last_k = -1;                     // iterations the last pd_parareal completed on the current
+                                       // state (-1: nothing pd_parareal_continue may go on from)
   bool have_gold = false;              // the resumed state came with the previous coarse values
   // device memory
   DevBuf tw, twc;                      // twiddles (fine, coarse)

@@ -108,6 +108,7 @@ pd_status pd_set_slices(pd_ctx* c, const double* U, const double* Gold, int k) {
   }
   c->have_initial = true;
   c->resume_k = k;
+  c->last_k = -1;
   return PD_OK;
 }
 

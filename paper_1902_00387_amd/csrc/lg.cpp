@@ -259,6 +259,8 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
   if (!c->lg.init) return fail(c, PD_ESTATE, "pd_lg_init not called");
   if (!c->have_initial) return fail(c, PD_ESTATE, "pd_set_initial not called");
   if (iters < 0 || iters >= c->P) return fail(c, PD_EINVAL, "iters must be in [0, n_slices)");
+  c->last_k = -1;
+  c->resume_k = -1;
   DeviceGuard dg(c->device);
   hipStream_t st = c->stream;
   const size_t box = c->box_elems(), rows = c->rows_elems(), full = (size_t)3 * c->N * c->N;
@@ -588,6 +590,10 @@ pd_status pd_lg_set_loss_decay(pd_ctx* c, double beta) {
 pd_status pd_set_coarse(pd_ctx* c, int learned) {
   if (!c) return PD_EINVAL;
   if (learned && !c->lg.init) return fail(c, PD_ESTATE, "pd_lg_init not called");
+  // switching to the plain propagator: the coarse values of the learned
+  // iterates are not there, so the state cannot be continued; the learned
+  // difference form needs only U^k, so switching to it keeps it continuable
+  if (!learned && c->lg.enabled) c->last_k = -1;
   c->lg.enabled = learned != 0;
   return PD_OK;
 }

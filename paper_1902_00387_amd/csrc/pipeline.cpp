@@ -268,6 +268,7 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, bool
   PD_HIP(c, hipEventRecord(evRed, cs), "event");
   PD_HIP(c, hipStreamWaitEvent(c->stream, evRed, 0), "wait");
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  c->last_k = status == PD_EUNSTABLE ? -1 : (r.iters > 0 ? r.iters : (kres >= 0 ? kres : 0));
   r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
   finish_report(r, P);
   if (rep) *rep = r;

@@ -446,6 +446,7 @@ static pd_status parareal_plain(pd_ctx* c, double tol, int max_iter, int kres, b
     }
   }
   if (max_iter == 0) status = PD_OK;
+  c->last_k = status == PD_EUNSTABLE ? -1 : (r.iters > 0 ? r.iters : (kres >= 0 ? kres : 0));
   r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
   finish_report(r, c->P);
   if (rep) *rep = r;
@@ -712,6 +713,7 @@ pd_status pd_set_scheme(pd_ctx* c, pd_scheme fine, pd_scheme coarse) {
     return fail(c, PD_EINVAL, "complex64 steps SBDF2 only");
   c->scheme_f = fine;
   c->scheme_c = coarse;
+  c->last_k = -1;
   DeviceGuard dg(c->device);
   return ensure_rk_buffers(c);
 }
@@ -743,6 +745,7 @@ pd_status pd_set_precision(pd_ctx* c, pd_prec prec) {
   c->sweep_next = -1;
   c->have_time = c->have_initial = false;
   c->resume_k = -1;
+  c->last_k = -1;
   lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
   c->T2f.release(); c->Uprev.release(); c->Bc.release(); c->Hc.release(); c->T1c.release();
@@ -763,6 +766,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   DeviceGuard dg(c->device);
   c->have_problem = c->have_time = c->have_initial = false;
   c->resume_k = -1;
+  c->last_k = -1;
   lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
   c->T2f.release(); c->Uprev.release();
@@ -797,6 +801,7 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   DeviceGuard dg(c->device);
   c->have_time = c->have_initial = false;
   c->resume_k = -1;
+  c->last_k = -1;
   lg_release(c);
   c->T = T; c->P = P; c->dT = dT; c->dtf = dtf; c->dtc = dtc; c->Nc = Nc; c->Mc = box_M(Nc);
   c->nf = nf; c->nc = nc;
@@ -866,6 +871,7 @@ pd_status pd_set_initial_dev(pd_ctx* c, const void* d_b0, void* s) {
   PD_HIP(c, hipStreamSynchronize(st), "sync");
   c->have_initial = true;
   c->resume_k = -1;
+  c->last_k = -1;
   return PD_OK;
 }
 
@@ -895,6 +901,7 @@ pd_status pd_set_initial(pd_ctx* c, const double* b0) {
   PD_HIP(c, hipStreamSynchronize(c->stream), "sync");
   c->have_initial = true;
   c->resume_k = -1;
+  c->last_k = -1;
   return PD_OK;
 }
 
@@ -941,6 +948,7 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   if (kres >= 0 && max_iter <= kres)
     return fail(c, PD_EINVAL, "max_iter must exceed the resumed iteration %d", kres);
   c->resume_k = -1;
+  c->last_k = -1;
   {
     pd_status rs = ensure_rk_buffers(c);
     if (rs != PD_OK) return rs;
@@ -948,6 +956,21 @@ pd_status pd_parareal(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
   if (c->pipe_chunks > 1) return parareal_pipelined(c, tol, max_iter, kres, rep);
   if (c->prec == PD_C64) return parareal_plain<cplxf>(c, tol, max_iter, kres, false, rep, wall0);
   return parareal_plain<cplx>(c, tol, max_iter, kres, learned, rep, wall0);
+}
+
+pd_status pd_parareal_continue(pd_ctx* c, double tol, int max_iter, pd_report* rep) {
+  if (!c) return PD_EINVAL;
+  c->err.clear();
+  if (!c->have_initial || c->last_k < 0)
+    return fail(c, PD_ESTATE, "no Parareal run on the current state to continue");
+  if (max_iter <= c->last_k || max_iter > PD_MAX_ITER)
+    return fail(c, PD_EINVAL, "max_iter must be in (%d, %d]", c->last_k, PD_MAX_ITER);
+  if (!(tol >= 0)) return fail(c, PD_EINVAL, "tol must be >= 0");
+  // the state after the last completed iteration is in place: U^k, and for
+  // the plain coarse propagator G(U^k_n) in Gold
+  c->resume_k = c->last_k;
+  c->have_gold = true;
+  return pd_parareal(c, tol, max_iter, rep);
 }
 
 pd_status pd_profile_fine(pd_ctx* c, int reps, double* ms) {

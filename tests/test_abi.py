@@ -38,6 +38,7 @@ def test_null_context_calls_fail_cleanly():
     assert pd.lib.pd_set_path(None, 0) == pd.EINVAL
     assert pd.lib.pd_set_fine_blocking(None, 2, 3) == pd.EINVAL
     assert pd.lib.pd_get_fine_blocking(None, None, None) == pd.EINVAL
+    assert pd.lib.pd_parareal_continue(None, 1e-8, 4, None) == pd.EINVAL
     assert pd.lib.pd_last_error(None) == b"null context"
     assert pd.lib.pd_create(None, 0) == pd.EINVAL
 

@@ -158,3 +158,87 @@ def test_seed_initial_is_the_reference_field(lib, N, kz, seed, kmax):
         U0 = ctx.get_slices()[0]
     ref = initial_field(N, kz, seed, amp=1e-3, kmax=kmax)
     assert np.array_equal(U0.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("chunks,learned", [(0, False), (3, False), (0, True), (2, True)])
+def test_parareal_continue_is_bitwise_an_uninterrupted_run(lib, chunks, learned):
+    """A solve run in pieces (pd_parareal to iteration 2, then
+    pd_parareal_continue to 4 and to the end) gives the iterates, defects and
+    k_con of one call, plain and pipelined, plain and learned coarse
+    propagator."""
+    N, P = 32, 8
+
+    def make():
+        ctx = lib.Context(0)
+        ctx.set_problem("gp", 60.0, 0.57, N)
+        ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, 16)
+        ctx.set_pipeline(chunks, 2)
+        if learned:
+            ctx.lg_init(2, 11)
+            ctx.set_coarse(True)
+        ctx.set_initial(initial_field(N, 0.57, 77))
+        return ctx
+
+    with make() as a:
+        ra = a.parareal(1e-10, P + 1)
+        Ua = a.get_slices()
+    with make() as b:
+        r1 = b.parareal(1e-10, 2)
+        assert r1["iters"] == 2 and r1["status"] == lib.NOT_CONVERGED
+        r2 = b.parareal_continue(1e-10, 4)
+        assert r2["iters"] == 4
+        r3 = b.parareal_continue(1e-10, P + 1)
+        Ub = b.get_slices()
+        with pytest.raises(lib.PitdynError):
+            b.parareal_continue(1e-10, r3["iters"])     # max_iter must exceed the last iteration
+    assert r3["k_con"] == ra["k_con"] and r3["iters"] == ra["iters"]
+    sig = r1["sigma"][:2] + r2["sigma"][2:4] + r3["sigma"][4:r3["iters"]]
+    assert sig == ra["sigma"][:ra["iters"]]
+    assert np.array_equal(Ua, Ub)
+
+
+def test_parareal_continue_needs_a_run_on_the_current_state(lib):
+    with lib.Context(0) as ctx:
+        ctx.set_problem("gp", 60.0, 0.57, 32)
+        ctx.set_time(2.0, 8, 5e-3, 2.5e-2, 16)
+        ctx.set_initial(initial_field(32, 0.57, 77))
+        with pytest.raises(lib.PitdynError):
+            ctx.parareal_continue(1e-10, 3)             # no run yet
+        ctx.parareal(1e-10, 1)
+        ctx.set_initial(initial_field(32, 0.57, 78))
+        with pytest.raises(lib.PitdynError):
+            ctx.parareal_continue(1e-10, 3)             # the state changed since
+        ctx.parareal(0.0, 0)                            # the initial coarse run only
+        r = ctx.parareal_continue(0.0, 2)
+        assert r["iters"] == 2
+
+
+def test_plain_then_learned_coarse_propagator(lib):
+    """Iterations 1-2 with the plain coarse propagator, then the learned one
+    (pd_set_coarse between pd_parareal and pd_parareal_continue): after P
+    iterations the result is the serial fine solution, bitwise the plain
+    run's (finite termination holds for any coarse propagator); switching
+    back to the plain propagator cannot continue (no coarse values)."""
+    N, P = 32, 6
+
+    def make():
+        ctx = lib.Context(0)
+        ctx.set_problem("gp", 60.0, 0.57, N)
+        ctx.set_time(0.25 * P, P, 5e-3, 2.5e-2, 16)
+        ctx.lg_init(2, 11)
+        ctx.set_initial(initial_field(N, 0.57, 77))
+        return ctx
+
+    with make() as a:
+        a.parareal(0.0, P)
+        Ua = a.get_slices()
+    with make() as b:
+        b.parareal(0.0, 2)
+        b.set_coarse(True)
+        r = b.parareal_continue(0.0, P)
+        assert r["iters"] == P
+        Ub = b.get_slices()
+        b.set_coarse(False)
+        with pytest.raises(lib.PitdynError):
+            b.parareal_continue(0.0, P + 1)
+    assert np.array_equal(Ua, Ub)
