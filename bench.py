@@ -374,11 +374,18 @@ def run_learned(args):
     ctx.set_time(T, P, w["dtf"], dtc, nc)
 
     def solve(learned):
-        ctx.set_coarse(learned)
+        switch = args.lg_switch if learned else 0
+        ctx.set_coarse(learned and switch == 0)
         ctx.set_initial(b0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = ctx.parareal(TOL, P + 1)
+        rep = ctx.parareal(TOL, switch if switch > 0 else P + 1)
+        if switch > 0 and rep["k_con"] < 0:
+            # plain G for the first iterations, then the learned propagator
+            sig = list(rep["sigma"])
+            ctx.set_coarse(True)
+            rep = ctx.parareal_continue(TOL, P + 1)
+            rep["sigma"] = sig + rep["sigma"][len(sig):]
         gam = ctx.growth_rate()
         torch.cuda.synchronize()
         return rep, gam, time.perf_counter() - t0
@@ -447,6 +454,7 @@ def run_learned(args):
                   "t_fine_s": rp["t_fine_s"], "t_coarse_s": rp["t_coarse_s"] + rp["t_coarse0_s"],
                   "sigma": rp["sigma"][:rp["iters"]]},
         "learned": {"k_con": rl["k_con"], "time_s": tl, "growth_rate": gl,
+                    "plain_iterations_first": args.lg_switch,
                     "t_fine_s": rl["t_fine_s"], "t_coarse_s": rl["t_coarse_s"] + rl["t_coarse0_s"],
                     "sigma": rl["sigma"][:rl["iters"]], "final_state_reldiff_vs_plain": diff},
         "serial_fine_gpu_s": serial_s,
@@ -1304,6 +1312,8 @@ def main():
     ap.add_argument("--lg-late", type=int, default=4,
                     help="--learned: train only on differences of iterations >= this (0: all)")
     ap.add_argument("--lg-steps", type=int, default=2000, help="--learned: Adam steps")
+    ap.add_argument("--lg-switch", type=int, default=4,
+                    help="--learned: plain G for this many iterations, then the learned one")
     ap.add_argument("--c64", action="store_true",
                     help="complex64 variant beside complex128 (fine step, 128^2 Parareal)")
     ap.add_argument("--p5-nc", type=int, default=128, help="--parareal5: coarse grid")
@@ -1317,7 +1327,7 @@ def main():
     ap.add_argument("--l5-iters", type=int, default=40, help="--learned5: iteration cap")
     ap.add_argument("--l5-harvest", type=int, default=8, help="--learned5: harvested iterations")
     ap.add_argument("--l5-steps", type=int, default=2000, help="--learned5: Adam steps")
-    ap.add_argument("--l5-switch", type=int, default=0,
+    ap.add_argument("--l5-switch", type=int, default=4,
                     help="--learned5: plain G for this many iterations, then the learned one")
     ap.add_argument("--blocking-sweep", action="store_true",
                     help="time the fine sweep for fine-blocking settings and launch shapes")

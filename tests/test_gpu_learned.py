@@ -237,5 +237,16 @@ def test_learned_coarse_propagator_needs_fewer_iterations(lib):
         rl = ctx.parareal(1e-8, P + 1)
         Ul = ctx.get_slices()
         print(f"learned G: k_con {rl['k_con']} in {rl['t_total_s']:.2f} s", flush=True)
+        # the schedule the network was trained for: plain G for iterations
+        # 1-4, the learned propagator from iteration 5 on
+        ctx.set_coarse(False)
+        ctx.set_initial(b0)
+        ctx.parareal(1e-8, K0)
+        ctx.set_coarse(True)
+        rh = ctx.parareal_continue(1e-8, P + 1)
+        Uh = ctx.get_slices()
+        print(f"plain then learned G: k_con {rh['k_con']}", flush=True)
     assert 0 < rl["k_con"] < rp["k_con"]
+    assert 0 < rh["k_con"] < rp["k_con"]
     assert relnorm(Ul[P], Up[P]) <= 1e-7
+    assert relnorm(Uh[P], Up[P]) <= 1e-7
