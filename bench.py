@@ -87,13 +87,49 @@ def _oracle_steps(job):
     return time.perf_counter() - t
 
 
+def _one_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _oracle_parareal_config1(workers):
+    """The oracle's Parareal on the Roberts 32^2 workload (Rm = 10, kz = 1,
+    T = 8 over 8 slices, fine dt = 1e-3, coarse dt = 1e-2, tol 1e-8) with
+    the fine solves of each iteration on worker processes, and its serial
+    fine solve, both timed."""
+    import multiprocessing as mp
+    from oracle import parareal as opr
+    from oracle import stepper
+    from synthetic import initial_field
+    N1, kz1, Rm1, T1, P1, dtf1, dtc1 = 32, 1.0, 10.0, 8.0, 8, 1e-3, 1e-2
+    b0 = initial_field(N1, kz1, 100000)
+    F = stepper.SliceSolver("roberts", Rm1, kz1, N1, T1 / P1, dtf1)
+    G = stepper.SliceSolver("roberts", Rm1, kz1, N1, T1 / P1, dtc1)
+    nw = max(1, min(workers, P1))
+    t0 = time.perf_counter()
+    opr.serial_fine(b0, P1, T1 / P1, F)
+    serial_s = time.perf_counter() - t0
+    with mp.get_context("fork").Pool(nw, initializer=_one_thread) as pool:
+        t0 = time.perf_counter()
+        r = opr.parareal(b0, P1, T1 / P1, F, G, tol=1e-8, max_iter=P1,
+                         fmap=lambda fn, xs, ts: pool.starmap(fn, zip(xs, ts)))
+        par_s = time.perf_counter() - t0
+    return {"workload": "Roberts Rm=10, kz=1, 32^2, T=8 over 8 slices, fine dt=1e-3, coarse "
+                        "dt=1e-2, tol 1e-8", "k_con": r.k_con, "time_s": par_s,
+            "serial_fine_s": serial_s, "workers": nw, "speedup": serial_s / par_s}
+
+
 def cpu_baseline(budget_s=15.0):
     """The FP64 oracle's fine propagator, timed on the host's cores on a
     bounded sample of the headline workload: one seeded 512^2 field per
     worker process (as the paper's time-parallel layout gives each processor
     its own slice), each advanced by the same number of fine steps, sized to
-    about `budget_s` of work a worker.  Runs before the GPU is touched (the
-    workers are forked)."""
+    about `budget_s` of work a worker; and the oracle's whole Parareal on the
+    small Roberts workload with its fine solves on worker processes.  Runs
+    before the GPU is touched (the workers are forked)."""
     import multiprocessing as mp
     ncpu = os.cpu_count() or 1
     workers = max(1, min(ncpu, CPU_WORKERS_MAX))
@@ -105,8 +141,9 @@ def cpu_baseline(budget_s=15.0):
         per = pool.map(_oracle_steps, jobs)
     wall = time.perf_counter() - t0
     done = workers * nsteps * N5 * N5
+    par = _oracle_parareal_config1(workers)
     return {"value": done / wall, "unit": "fine mode-steps/s", "cores": workers,
-            "host_cpu_count": ncpu, "kind": "oracle",
+            "host_cpu_count": ncpu, "kind": "oracle", "parareal": par,
             "sample": f"{workers} worker processes x {nsteps} fine SBDF2 steps of one seeded "
                       f"{N5}^2 field each (Rm={RM5:g}), {wall:.1f} s wall, "
                       f"{min(per):.1f}-{max(per):.1f} s a worker; a whole slice is 2000 steps"}

@@ -60,13 +60,18 @@ def serial_fine(U0: np.ndarray, P: int, dT: float, F) -> list:
 
 def parareal(U0: np.ndarray, P: int, dT: float, F, G, tol: float,
              max_iter: int, form: str = "standard",
-             keep_history: bool = False) -> PararealResult:
+             keep_history: bool = False, fmap=None) -> PararealResult:
     """Run Parareal until sigma_k <= tol or k = max_iter.
 
     ``form`` is ``"standard"`` (store G(U^{k-1}_n) and correct with
     F + (G_new - G_old)) or ``"difference"`` (F + G(U^k_n - U^{k-1}_n),
-    valid for linear G).
+    valid for linear G).  ``fmap(F, states, times)`` applies F to the
+    slices of one iteration and returns the results in slice order (default:
+    the built-in ``map``, one slice after another); the fine solves of an
+    iteration are independent (Section 3), so a process pool's ``map`` may
+    run them concurrently.
     """
+    fmap = map if fmap is None else fmap
     if form not in ("standard", "difference"):
         raise ValueError(form)
     U = coarse_sweep(U0, P, dT, G)
@@ -75,7 +80,7 @@ def parareal(U0: np.ndarray, P: int, dT: float, F, G, tol: float,
     if keep_history:
         res.history.append([u.copy() for u in U])
     for k in range(1, max_iter + 1):
-        f = [F(U[n], n * dT) for n in range(P)]
+        f = list(fmap(F, [U[n] for n in range(P)], [n * dT for n in range(P)]))
         V = [U[0]]
         for n in range(P):
             if form == "standard":

@@ -71,6 +71,26 @@ def test_difference_form_equals_standard_for_linear_G():
     assert np.allclose(a.sigma, b.sigma, rtol=1e-6, atol=1e-15)
 
 
+def test_fine_solves_in_any_order_or_processes_give_the_same_iterates():
+    """The fine solves of one iteration are independent (Section 3): applied
+    in reverse slice order, or in worker processes, they give bitwise the
+    serial iterates."""
+    import multiprocessing as mp
+    F, G, b0, P, dT = _setup(flow="gp", Nc=8, P=5)
+    a = pr.parareal(b0, P, dT, F, G, tol=0.0, max_iter=2)
+
+    def reverse_map(fn, xs, ts):
+        out = [fn(x, t) for x, t in reversed(list(zip(xs, ts)))]
+        return list(reversed(out))
+    b = pr.parareal(b0, P, dT, F, G, tol=0.0, max_iter=2, fmap=reverse_map)
+    with mp.get_context("fork").Pool(2) as pool:
+        c = pr.parareal(b0, P, dT, F, G, tol=0.0, max_iter=2,
+                        fmap=lambda fn, xs, ts: pool.starmap(fn, zip(xs, ts)))
+    for n in range(P + 1):
+        assert np.array_equal(a.U[n], b.U[n]) and np.array_equal(a.U[n], c.U[n])
+    assert a.sigma == b.sigma == c.sigma
+
+
 def test_defect_and_k_con():
     F, G, b0, P, dT = _setup(flow="gp", Nc=16, P=6)
     r = pr.parareal(b0, P, dT, F, G, tol=1e-4, max_iter=6, keep_history=True)
