@@ -66,6 +66,26 @@ struct LdsSpan {
 template <int N>
 __device__ __forceinline__ int lpad(int i) { return i + (i >> LdsSpan<N>::shift); }
 
+// LDS slot of entry i of a transform's span.  A 16-byte access of a
+// wavefront is served 16 lanes at a time, conflict-free when the 16 lanes'
+// slots differ modulo 16.  The padded layout lpad does that for the
+// scatters (lanes 8 entries apart) but leaves one two-way conflict in every
+// 16 lanes of the gathers (entries j, j + 1, ... cross a padding slot).  For
+// the 512-point transform with 8 values a lane (passes with sub-transform
+// lengths 1, 8, 64) the permutation that XORs index bits 0-2 with bits 3-5
+// and bit 3 with bit 6 keeps all three patterns conflict-free: the gathers
+// j + 64 e (bits 0-3 vary), the first scatter 8 j + k (bits 3-6 vary) and
+// the second 64 (j / 8) + 8 k + j % 8 (bits 0-2 and 6 vary) each map their
+// 16 lanes onto 16 distinct slots.  Complex64 spans (8-byte entries) keep
+// the padded layout.
+template <int N, int E, class C>
+__device__ __forceinline__ int lidx(int i) {
+  if constexpr (N == 512 && E == 8 && sizeof(C) == 16)
+    return i ^ ((i >> 3) & 7) ^ (((i >> 6) & 1) << 3);
+  else
+    return lpad<N>(i);
+}
+
 // ---- small DFTs in registers ---------------------------------------------
 template <int DIR, class C>
 __device__ __forceinline__ void dft2(C& a, C& b) {
@@ -177,7 +197,7 @@ struct TwRegs {
 // One Stockham pass of radix R over sub-transforms of length NS, E values a
 // lane.  Lane j owns butterflies b = j + T*q, q < E/R (T = N/E lanes); wl
 // holds its (E/R) * (R-1) twiddles of this pass.  Outputs are scattered to
-// LDS (padded), then the lane reads back its strided values.  In the last
+// LDS (slots lidx), then the lane reads back its strided values.  In the last
 // pass (NS * R = N) output k of butterfly b lands at b + k*NS = j + T*(q +
 // Q*k), which is the lane's own strided register q + Q*k: the butterfly runs
 // in place in registers and the pass needs no exchange.
@@ -220,11 +240,11 @@ __device__ __forceinline__ void fft_pass(C* v, C* s, int j, const C* wl) {
     dftR<R, DIR>(x);
     const int base = (b / NS) * NS * R + jj;
 #pragma unroll
-    for (int k = 0; k < R; ++k) s[lpad<N>(base + k * NS)] = x[k];
+    for (int k = 0; k < R; ++k) s[lidx<N, E, C>(base + k * NS)] = x[k];
   }
   group_sync();
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = s[lpad<N>(j + T * e)];
+  for (int e = 0; e < E; ++e) v[e] = s[lidx<N, E, C>(j + T * e)];
   group_sync();
 }
 

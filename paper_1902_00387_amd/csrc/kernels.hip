@@ -233,8 +233,18 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
   constexpr int T = G::T, K = G::K, M = G::M;
   constexpr int nthr = LANES;
   constexpr int TX = nthr / T < N ? nthr / T : N;
-  constexpr int TP = TX + 1;
-  constexpr int TS = M * TP;  // one component's tile
+  // Tile rows R = c M + r (component c, box row r), TP slots each.  A
+  // 16-byte access is served 16 lanes at a time, conflict-free when their
+  // slots differ modulo 16.  Complex128 tiles are unpadded and the column is
+  // XOR-swizzled by the row: the staging (16 lanes = 16/TX rows x TX
+  // columns, rows aligned) and the column reads (16 consecutive rows, one
+  // column) then both meet 16 distinct slots.  Complex64 tiles (8-byte
+  // entries) keep one padding slot a row.
+  constexpr bool SW = sizeof(C) == 16;
+  constexpr int TP = SW ? TX : TX + 1;
+  constexpr int RPB = TX >= 16 ? 1 : 16 / TX;  // rows a 16-slot line
+  constexpr int FM = (TX < 16 ? TX : 16) - 1;
+  const auto tslot = [](int R, int col) { return R * TP + (SW ? (col ^ ((R / RPB) & FM)) : col); };
   const int tid = threadIdx.x;
   const int g = tid / T, j = tid % T;
   const int x = x0 + g;
@@ -253,7 +263,6 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
   const int cc = tid % TX, R0 = tid / TX;
   const bool cin = x0 + cc < N;
   const C* src = T1 + (size_t)R0 * N + x0 + cc;
-  C* tl = tile + R0 * TP + cc;
 #pragma unroll 1
   for (int i0 = 0; i0 < NIT; i0 += CH) {
     C buf[CH];
@@ -265,7 +274,7 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int R = R0 + (i0 + q) * RPL;
-      if (i0 + q < NIT && R < 3 * M) tl[(i0 + q) * RPL * TP] = buf[q];
+      if (i0 + q < NIT && R < 3 * M) tile[tslot(R, cc)] = buf[q];
     }
   }
   __syncthreads();
@@ -275,7 +284,7 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = signed_k(j + T * e, N);
-      w[c][e] = (active && ky >= -K && ky <= K) ? tile[c * TS + (ky + K) * TP + g] : zero_of<C>();
+      w[c][e] = (active && ky >= -K && ky <= K) ? tile[tslot(c * M + ky + K, g)] : zero_of<C>();
     }
   __syncthreads();
   if (g < TX) {
@@ -310,7 +319,7 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int ky = signed_k(j + T * e, N);
-        if (ky >= -K && ky <= K) tile[c * TS + (ky + K) * TP + g] = w[c][e];
+        if (ky >= -K && ky <= K) tile[tslot(c * M + ky + K, g)] = w[c][e];
       }
   }
   __syncthreads();
@@ -321,7 +330,7 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int R = R0 + (i0 + q) * RPL;
-      buf[q] = (i0 + q < NIT && R < 3 * M) ? tl[(i0 + q) * RPL * TP] : zero_of<C>();
+      buf[q] = (i0 + q < NIT && R < 3 * M) ? tile[tslot(R, cc)] : zero_of<C>();
     }
 #pragma unroll
     for (int q = 0; q < CH; ++q) {

@@ -5,6 +5,8 @@ launch configuration the benchmark times; the oracle recomputes sampled
 slices step by step (a whole 2000-step slice costs the oracle minutes, so
 the samples take a few steps).  Bar: 1e-12 relative L2."""
 import ctypes
+import json
+import os
 
 import numpy as np
 import pytest
@@ -88,3 +90,39 @@ def test_config5_stepwise_sweep_matches_oracle(lib):
         y = ctx.get_fine_states_dev(200, 1)[0].cpu().numpy()
         ref = stepper.propagate(start[200], "gp", RM, KZ, 200 * (T / P), DTF, 4)
         assert rel(y, ref) <= TOL, rel(y, ref)
+
+
+GOLD5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config5_slice_oracle.json")
+
+
+def test_config5_whole_slice_matches_oracle(lib):
+    """F over one whole slice (2000 fine steps) of the 512^2 workload, for four
+    seeded whole-box fields starting at slices 0, 37, 128, 255, in one batch
+    (blocked as the library does by default), against the oracle's results
+    stored by tests/golden/make_config5_slice.py: the norm of each result and
+    of its components, and 483 sampled coefficients, each within 1e-12 of the
+    result's norm."""
+    import torch
+    with open(GOLD5) as fh:
+        gold = json.load(fh)
+    fields = gold["fields"]
+    x = torch.from_numpy(np.stack([seeded(lib, f["seed"]) for f in fields])).cuda()
+    t0 = np.array([f["t0"] for f in fields])
+    with lib.Context(0) as ctx:
+        ctx.set_problem("gp", RM, KZ, N)
+        ctx.set_time(T, P, DTF, 2.5e-3, 64)
+        print(f"config5 whole slice: {len(fields)} fields, blocking {ctx.fine_blocking()}", flush=True)
+        y = ctx.fine(t0, x).cpu().numpy()
+    worst = 0.0
+    for f, yi in zip(fields, y):
+        nrm = f["norm"]
+        assert abs(np.linalg.norm(yi) - nrm) <= TOL * nrm, (f["seed"], np.linalg.norm(yi), nrm)
+        for c in range(3):
+            cn = f["component_norms"][c]
+            assert abs(np.linalg.norm(yi[c]) - cn) <= TOL * nrm
+        for c, ky, kx, re, im in f["samples"]:
+            e = abs(yi[c, ky % N, kx % N] - complex(re, im)) / nrm
+            worst = max(worst, e)
+            assert e <= TOL, (f["seed"], c, ky, kx, e)
+    print(f"worst sampled coefficient difference / norm: {worst:.2e}", flush=True)
+
