@@ -134,8 +134,10 @@ int choose_path(const pd_ctx* c, int nfields);
 // batch of nfields fields
 void fine_blocking(const pd_ctx* c, int nfields, int* group, int* streams);
 // Enqueue `run(sub_batch, fields, stream)` for consecutive groups of `group`
-// fields of fb, dealt round-robin to `streams` streams (st first, then the
-// context's idle pipeline streams), forked from and joined back into st.
+// fields of fb (fields on the context's fine grid: sub-batches are offset by
+// its box and row sizes), dealt round-robin to `streams` streams (st first,
+// then the context's idle pipeline streams), forked from and joined back
+// into st.
 // the streams of a blocked sweep (st first, at most 3) and the fork event
 // recorded on st that the others wait for; returns how many there are
 int blocking_fork(pd_ctx* c, int streams, hipStream_t st, hipStream_t* out, hipError_t* err);

@@ -223,6 +223,10 @@ __device__ __forceinline__ void fft_pass(C* v, C* s, int j, const C* wl) {
     }
     return;
   }
+  // the swizzled 512-point layout with its slots written out per pattern
+  // (the same slots as lidx, with the lane's part computed once)
+  constexpr bool SWZ = N == 512 && E == 8 && sizeof(C) == 16;
+  static_assert(!SWZ || Q == 1, "one butterfly a lane in the swizzled passes");
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int b = j + T * q;
@@ -238,13 +242,32 @@ __device__ __forceinline__ void fft_pass(C* v, C* s, int j, const C* wl) {
       }
     }
     dftR<R, DIR>(x);
-    const int base = (b / NS) * NS * R + jj;
+    if constexpr (SWZ && NS == 1) {
+      // entries 8 j + k: slot ((8 j) ^ (8 bit3(j))) + (k ^ (j & 7))
+      const int hi = (8 * j) ^ (((j >> 3) & 1) << 3), lo = j & 7;
 #pragma unroll
-    for (int k = 0; k < R; ++k) s[lidx<N, E, C>(base + k * NS)] = x[k];
+      for (int k = 0; k < R; ++k) s[hi + (k ^ lo)] = x[k];
+    } else if constexpr (SWZ && NS == 8) {
+      // entries 64 (j / 8) + 8 k + j % 8: slot 64 (j / 8) + 8 (k ^ bit3(j)) + ((j & 7) ^ k)
+      const int hi = 64 * (j >> 3), c1 = (j >> 3) & 1, lo = j & 7;
+#pragma unroll
+      for (int k = 0; k < R; ++k) s[hi + 8 * (k ^ c1) + (lo ^ k)] = x[k];
+    } else {
+      const int base = (b / NS) * NS * R + jj;
+#pragma unroll
+      for (int k = 0; k < R; ++k) s[lidx<N, E, C>(base + k * NS)] = x[k];
+    }
   }
   group_sync();
+  if constexpr (SWZ) {
+    // entries j + 64 e: slot (j ^ ((j >> 3) & 7) ^ (8 (e & 1))) + 64 e
+    const int jg = j ^ ((j >> 3) & 7);
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = s[lidx<N, E, C>(j + T * e)];
+    for (int e = 0; e < E; ++e) v[e] = s[(jg ^ ((e & 1) << 3)) + T * e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = s[lidx<N, E, C>(j + T * e)];
+  }
   group_sync();
 }
 
