@@ -358,8 +358,9 @@ pd_status pd_get_fine_states_dev(const pd_ctx* ctx, int first, int count, void* 
    pd_set_fine_blocking overrides it).  The choice belongs to this context (it applies to
    its fine propagator calls, sweeps and pd_parareal until the next
    pd_set_problem); other contexts keep theirs.  With cache_path non-NULL the choice is first looked
-   up in that JSON file (key "<gfx arch>|<N>|<n_slices>", value [rows, cols,
-   group, streams]; ms = 0 on a hit) and stored there after timing.  Variants give identical results bitwise only
+   up in that JSON file (key "<gfx arch>|hip<runtime version>|<N>|<n_slices>",
+   value [rows, cols, group, streams]; ms = 0 on a hit) and stored there
+   after timing.  Variants give identical results bitwise only
    with equal values a lane; all agree with the oracle to the parity bar. */
 pd_status pd_autotune(pd_ctx* ctx, int reps, const char* cache_path, int* chosen, double* ms);
 /* Variant table: v = -1 puts the number of variants of `kind` (0 rows,

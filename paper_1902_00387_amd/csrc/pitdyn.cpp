@@ -1003,13 +1003,17 @@ pd_status pd_fine_sweep_steps(pd_ctx* c, int step0, int n_steps, double* ms) {
 
 namespace {
 
+// cache key: gfx architecture, HIP runtime version (launch shapes tuned
+// under one runtime and compiler need not suit another), grid, batch
 std::string tune_key(int device, int N, int P) {
   hipDeviceProp_t prop;
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
   const size_t colon = arch.find(':');
   if (colon != std::string::npos) arch = arch.substr(0, colon);
-  return arch + "|" + std::to_string(N) + "|" + std::to_string(P);
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+  return arch + "|hip" + std::to_string(rt) + "|" + std::to_string(N) + "|" + std::to_string(P);
 }
 
 // The cache is a flat JSON object {"<arch>|<N>|<batch>": [rows, cols], ...}.
