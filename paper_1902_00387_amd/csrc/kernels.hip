@@ -262,19 +262,41 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ 
   constexpr int NIT = (3 * M + RPL - 1) / RPL;       // passes
   const int cc = tid % TX, R0 = tid / TX;
   const bool cin = x0 + cc < N;
-  const C* src = T1 + (size_t)R0 * N + x0 + cc;
+  if constexpr (SW && TX <= 64) {
+    // complex128: global memory straight into LDS (global_load_lds, 16
+    // bytes a lane): the 64 lanes of wave w fill the 64 consecutive slots
+    // from slot (w 64 / TX + it RPL) TX on, lane l the slot of row R0 + it
+    // RPL and swizzled position l % TX, so it loads the column (l % TX) ^
+    // f(row) that tslot places there.  No registers, every pass in flight.
+    static_assert(N % TX == 0, "whole tiles");
+    typedef __attribute__((address_space(3))) void lds_void;
+    const int wbase = (tid >> 6) * (64 / TX);
 #pragma unroll 1
-  for (int i0 = 0; i0 < NIT; i0 += CH) {
-    C buf[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int R = R0 + (i0 + q) * RPL;
-      buf[q] = (i0 + q < NIT && R < 3 * M && cin) ? src[(size_t)(i0 + q) * RPL * N] : zero_of<C>();
+    for (int it = 0; it < NIT; ++it) {
+      const int R = R0 + it * RPL;
+      if (R < 3 * M) {
+        const int col = cc ^ ((R / RPB) & FM);
+        __builtin_amdgcn_global_load_lds(
+            static_cast<const void*>(T1 + (size_t)R * N + x0 + col),
+            (lds_void*)(tile + (wbase + it * RPL) * TX), 16, 0, 0);
+      }
     }
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    const C* src = T1 + (size_t)R0 * N + x0 + cc;
+#pragma unroll 1
+    for (int i0 = 0; i0 < NIT; i0 += CH) {
+      C buf[CH];
 #pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int R = R0 + (i0 + q) * RPL;
-      if (i0 + q < NIT && R < 3 * M) tile[tslot(R, cc)] = buf[q];
+      for (int q = 0; q < CH; ++q) {
+        const int R = R0 + (i0 + q) * RPL;
+        buf[q] = (i0 + q < NIT && R < 3 * M && cin) ? src[(size_t)(i0 + q) * RPL * N] : zero_of<C>();
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int R = R0 + (i0 + q) * RPL;
+        if (i0 + q < NIT && R < 3 * M) tile[tslot(R, cc)] = buf[q];
+      }
     }
   }
   __syncthreads();
