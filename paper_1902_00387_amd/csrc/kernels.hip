@@ -444,6 +444,18 @@ __global__ __launch_bounds__(3 * (N / E)) void k_rows_c3(FieldBatchT<C> fb, Prob
     fft<N, E, -1>(w, s, j, twr);
 #pragma unroll
     for (int e = 0; e < E; ++e) s[j + T * e] = w[e];
+    // this wave's own entries of B and H, fetched before the barrier so that
+    // their latency overlaps it (no other wave writes them)
+    C bq[E], hq[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = signed_k(j + T * e, N);
+      if (kx >= -K && kx <= K) {
+        const int idx = (c * M + r) * M + kx + K;
+        bq[e] = B[idx];
+        hq[e] = mode == 1 ? zero_of<C>() : H[idx];
+      }
+    }
     __syncthreads();
     const C* s1 = sm + ((c + 1) % 3) * SP;  // the next and the one after (cyclic)
     const C* s2 = sm + ((c + 2) % 3) * SP;
@@ -466,14 +478,14 @@ __global__ __launch_bounds__(3 * (N / E)) void k_rows_c3(FieldBatchT<C> fb, Prob
           nl = mul_i<1>(csub(cscale(o2, dkx), cscale(o1, dky)));
         const Rl a = dt * (dkx * dkx + dky * dky + kz * kz) / Rm;
         const int idx = (c * M + r) * M + kx + K;
-        const C b = B[idx];
+        const C b = bq[e];
         C bn;
         if (mode == 1) {
           const Rl inv = (Rl)1 / ((Rl)1 + a);
           bn = cscale(cadd(b, cscale(nl, dt)), inv);
         } else {
           const Rl inv = (Rl)1 / ((Rl)1.5 + a);
-          bn = cscale(cadd(cadd(cscale(b, (Rl)2), cscale(nl, (Rl)2 * dt)), H[idx]), inv);
+          bn = cscale(cadd(cadd(cscale(b, (Rl)2), cscale(nl, (Rl)2 * dt)), hq[e]), inv);
         }
         H[idx] = csub(cscale(b, (Rl)-0.5), cscale(nl, dt));
         B[idx] = bn;
