@@ -284,7 +284,7 @@ pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate);
    state, history and row buffers stay in the device's last-level cache
    across its steps instead of streaming through HBM at every step.
    group = 0: off (every step runs over the whole batch); group = -1
-   (default): groups of 3 fields on 3 streams at 512^2, of 16 fields on 2
+   (default): groups of 4 fields on 3 streams at 512^2, of 16 fields on 3
    streams at 256^2, off on smaller grids.  Applies to the multi-launch path (fine sweeps of pd_parareal,
    pd_fine_dev / pd_steps_dev batches, pd_fine_sweep_steps, pd_profile_fine);
    in the pipelined schedule each run of slices is blocked on its own fine

@@ -51,7 +51,7 @@ struct Cls {
   double dtf = 0;
   int nfields = 0, nU = 0;
   std::vector<int> finst, fslice;  // instance and slice of each field
-  DevBuf U, Fo, Gold, H, T1, T2, t0, fRm, fkz, uidx, map, count, tw;
+  DevBuf U, Fo, Gold, H, T1, t0, fRm, fkz, uidx, map, count, tw;
   int* hmap = nullptr;  // pinned host staging: [nfields] map then [1] count
   hipStream_t side = nullptr;
   hipEvent_t done_ev = nullptr;
@@ -202,7 +202,6 @@ pd_status build(pd_batch* b) {
     PB_HIP(b, c.Gold.ensure(sizeof(cplx) * box * c.nfields), "alloc Gold");
     PB_HIP(b, c.H.ensure(sizeof(cplx) * box * c.nfields), "alloc H");
     PB_HIP(b, c.T1.ensure(sizeof(cplx) * rows * c.nfields), "alloc T1");
-    PB_HIP(b, c.T2.ensure(sizeof(cplx) * rows * c.nfields), "alloc T2");
     PB_HIP(b, c.t0.ensure(sizeof(double) * c.nfields), "alloc");
     PB_HIP(b, c.fRm.ensure(sizeof(double) * c.nfields), "alloc");
     PB_HIP(b, c.fkz.ensure(sizeof(double) * c.nfields), "alloc");
@@ -315,7 +314,7 @@ hipError_t enqueue_iteration(pd_batch* b) {
     fb.B = c.Fo.as<cplx>();
     fb.H = c.H.as<cplx>();
     fb.T1 = c.T1.as<cplx>();
-    fb.T2 = c.T2.as<cplx>();
+    fb.T2 = fb.T1;  // in place
     fb.t0 = c.t0.as<double>();
     fb.tw = c.tw.as<cplx>();
     fb.fRm = c.fRm.as<double>();

@@ -53,13 +53,13 @@ struct pd_ctx {
   // device memory
   DevBuf tw, twc;                      // twiddles (fine, coarse)
   DevBuf twf, twcf;                    // the same in FP32 (complex64 variant)
-  DevBuf U, Fo, Gold, Hf, T1f, T2f;    // slice buffers
+  DevBuf U, Fo, Gold, Hf, T1f;         // slice buffers (the fine row phases work in place in T1f)
   DevBuf Uprev, t0s;                   // defect copy, slice start times
   DevBuf Bc, Hc, T1c, T2c;             // coarse sweep workspaces
   DevBuf red, flag;                    // reduction outputs, box-check flag
   DevBuf ftab;                         // flow phases at every coarse step time
   DevBuf Rf, Rc, wR;                   // Runge-Kutta stage sums: slices, coarse sweep, propagator calls
-  DevBuf wB, wH, wT1, wT2, wt0;        // workspaces of the propagator calls
+  DevBuf wB, wH, wT1, wt0;             // workspaces of the propagator calls
   double* hred = nullptr;              // pinned host copy of red
   // learned coarse propagator (correction network) state
   struct LG {

@@ -114,8 +114,8 @@ __device__ __forceinline__ cplx rk_update(cplx nl, double L, double d, double dt
 // end of Runge-Kutta stage j (stage sums in R).  last: skip the inverse.
 template <int N, int E, int RKS = 0, bool PF = false, class C = cplx>
 __device__ __forceinline__ void row_phase(int r, bool active, int j, C* s, C* __restrict__ B,
-                                          C* __restrict__ H, const C* __restrict__ T2,
-                                          C* __restrict__ T1, const C* __restrict__ tw,
+                                          C* __restrict__ H, const C* T2, C* T1,
+                                          const C* __restrict__ tw,
                                           const Problem& pb, int mode, bool last,
                                           C* __restrict__ R = nullptr) {
   using G = Geo<N, E>;
@@ -225,8 +225,8 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, C* s, C* __
 // are in flight at once; once every group holds its column in registers the
 // tile memory doubles as the groups' FFT exchange spans.
 template <int N, int E, int LANES, int CH, class C = cplx>
-__device__ __forceinline__ void col_tile(int x0, C* tile, const C* __restrict__ T1,
-                                         C* __restrict__ T2, const C* __restrict__ tw,
+__device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
+                                         const C* __restrict__ tw,
                                          const FlowPhase& fp) {
   using G = Geo<N, E>;
   using Rl = decltype(C::re);
@@ -423,8 +423,8 @@ __global__ __launch_bounds__(3 * (N / E)) void k_rows_c3(FieldBatchT<C> fb, Prob
   const size_t box = (size_t)3 * M * M, rows = (size_t)3 * M * N;
   C* __restrict__ B = fb.B + f * box;
   C* __restrict__ H = fb.H + f * box;
-  C* __restrict__ T1 = fb.T1 + f * rows;
-  const C* __restrict__ T2 = fb.T2 + f * rows;
+  C* T1 = fb.T1 + f * rows;
+  const C* T2 = fb.T2 + f * rows;  // may be T1 itself (see FieldBatchT)
   const Rl Rm = (Rl)(fb.fRm != nullptr ? fb.fRm[f] : pb.Rm);
   const Rl kz = (Rl)(fb.fkz != nullptr ? fb.fkz[f] : pb.kz);
   C* s = sm + c * SP;

@@ -38,8 +38,13 @@ template <class C>
 struct FieldBatchT {
   C* B = nullptr;              // [f][3][M][M] state (in: start value, out: end value)
   C* H = nullptr;              // [f][3][M][M] SBDF2 history workspace
-  C* T1 = nullptr;             // [f][3][M][N] row workspace
-  C* T2 = nullptr;             // [f][3][M][N] row workspace
+  // [f][3][M][N] row workspaces: the row phase reads T2 and writes T1, the
+  // column phase reads T1 and writes T2.  Each phase reads a row (a column
+  // tile) before it writes the same row (tile), and no other workgroup touches
+  // it, so T2 may be T1 itself: the library's fine buffers work in place,
+  // which keeps a slice's buffers a third smaller in the last-level cache.
+  C* T1 = nullptr;
+  C* T2 = nullptr;
   const double* t0 = nullptr;  // [f] start time of each field's slice
   const C* tw = nullptr;       // [N] twiddles e^{-2 pi i m/N}
   C* R = nullptr;              // [f][4][3][M][M] Runge-Kutta stage sums (scheme 1 only)

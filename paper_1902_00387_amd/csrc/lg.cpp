@@ -317,7 +317,7 @@ pd_status pd_lg_add_parareal_samples(pd_ctx* c, int iters, int* n_stored) {
       fb.B = c->Fo.as<cplx>() + (size_t)n0 * box;
       fb.H = c->Hf.as<cplx>() + (size_t)n0 * box;
       fb.T1 = c->T1f.as<cplx>() + (size_t)n0 * rows;
-      fb.T2 = c->T2f.as<cplx>() + (size_t)n0 * rows;
+      fb.T2 = fb.T1;
       fb.t0 = c->t0s.as<double>() + n0;
       fb.tw = c->tw.as<cplx>();
       c->shapes(fb);

@@ -160,7 +160,7 @@ static pd_status pipelined_t(pd_ctx* c, double tol, int max_iter, int kres, bool
         fb.B = Fo + (size_t)a * box;
         fb.H = c->Hf.as<CT>() + (size_t)a * box;
         fb.T1 = c->T1f.as<CT>() + (size_t)a * rows;
-        fb.T2 = c->T2f.as<CT>() + (size_t)a * rows;
+        fb.T2 = fb.T1;
         fb.t0 = c->t0s.as<double>() + a;
         fb.tw = c->twid<CT>();
         c->shapes(fb);

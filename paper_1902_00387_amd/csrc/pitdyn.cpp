@@ -138,21 +138,22 @@ int choose_path(const pd_ctx* c, int nfields) {
 }
 
 // Temporal blocking of fine sweeps.  A step of the whole batch streams every
-// field's state, history and both row buffers through HBM (213 B a grid mode
-// at 512^2, about 14 GB a step for 256 fields); a group of a few fields that
-// runs all its steps back to back keeps its 28 MB a field (512^2) in the
-// 256 MB memory-side last-level cache from one step to the next, and the
-// phases of groups on different streams overlap.  Defaults measured on
-// MI355X (K steps of every slice, best launch shapes): 512^2 x 256 fields,
-// groups of 3 on 3 streams, 2.51-2.66 against 3.24 ms a step unblocked;
-// 256^2 x 128, groups of 16 on 2 streams, 0.353 against 0.405 ms; 128^2 x 64
-// gains under 10 % (its whole batch, about 200 MB, already fits the cache)
-// and stays unblocked.
+// field's state, history and row buffer through HBM (213 B a grid mode at
+// 512^2, about 14 GB a step for 256 fields); a group of a few fields that
+// runs all its steps back to back keeps its 19.6 MB a field (512^2: state,
+// history, one row buffer used in place) in the 256 MB memory-side
+// last-level cache from one step to the next, and the phases of groups on
+// different streams overlap.  Defaults measured on MI355X (40 steps of every
+// slice, best launch shapes): 512^2 x 256 fields, groups of 4 on 3 streams,
+// 2.50 against 3.22 ms a step unblocked; 256^2 x 128, groups of 16 on 3
+// streams, 0.322 against 0.387 ms; 128^2 x 64 gains 7 % with groups of 32
+// (half its batch: a size that depends on the slice count) and stays
+// unblocked by default.
 void fine_blocking(const pd_ctx* c, int nfields, int* group, int* streams) {
   int g = c->blk_g, s = c->blk_s;
   if (g < 0) {
-    g = c->N >= 512 ? 3 : c->N == 256 ? 16 : 0;
-    s = c->N >= 512 ? 3 : 2;
+    g = c->N >= 512 ? 4 : c->N == 256 ? 16 : 0;
+    s = 3;
   }
   if (g >= nfields) g = 0;
   *group = g;
@@ -261,7 +262,6 @@ static pd_status run_propagator_t(pd_ctx* c, const double* t0, int batch, double
   PD_HIP(c, c->wB.ensure(box * batch * sizeof(C)), "alloc");
   PD_HIP(c, c->wH.ensure(box * batch * sizeof(C)), "alloc");
   PD_HIP(c, c->wT1.ensure(rows * batch * sizeof(C)), "alloc");
-  PD_HIP(c, c->wT2.ensure(rows * batch * sizeof(C)), "alloc");
   PD_HIP(c, c->wt0.ensure(sizeof(double) * batch), "alloc");
   PD_HIP(c, hipMemcpyAsync(c->wt0.p, t0, sizeof(double) * batch, hipMemcpyHostToDevice, st),
          "copy t0");
@@ -279,7 +279,7 @@ static pd_status run_propagator_t(pd_ctx* c, const double* t0, int batch, double
   fb.B = c->wB.as<C>();
   fb.H = c->wH.as<C>();
   fb.T1 = c->wT1.as<C>();
-  fb.T2 = c->wT2.as<C>();
+  fb.T2 = fb.T1;  // in place
   fb.t0 = c->wt0.as<double>();
   fb.tw = twg;
   if constexpr (sizeof(C) == sizeof(cplx)) {
@@ -404,7 +404,7 @@ static pd_status parareal_plain(pd_ctx* c, double tol, int max_iter, int kres, b
     fb.B = Fo + (size_t)n0 * box;
     fb.H = c->Hf.as<C>() + (size_t)n0 * box;
     fb.T1 = c->T1f.as<C>() + (size_t)n0 * rows;
-    fb.T2 = c->T2f.as<C>() + (size_t)n0 * rows;
+    fb.T2 = fb.T1;
     fb.t0 = c->t0s.as<double>() + n0;
     fb.tw = c->twid<C>();
     c->shapes(fb);
@@ -472,7 +472,7 @@ static pd_status profile_fine_t(pd_ctx* c, int reps, double* ms) {
   fb.B = c->Fo.as<C>();
   fb.H = c->Hf.as<C>();
   fb.T1 = c->T1f.as<C>();
-  fb.T2 = c->T2f.as<C>();
+  fb.T2 = fb.T1;
   fb.t0 = c->t0s.as<double>();
   fb.tw = c->twid<C>();
   c->shapes(fb);
@@ -517,7 +517,7 @@ static pd_status fine_sweep_steps_t(pd_ctx* c, int step0, int n_steps, double* m
   fb.B = c->Fo.as<C>();
   fb.H = c->Hf.as<C>();
   fb.T1 = c->T1f.as<C>();
-  fb.T2 = c->T2f.as<C>();
+  fb.T2 = fb.T1;
   fb.t0 = c->t0s.as<double>();
   fb.tw = c->twid<C>();
   c->shapes(fb);
@@ -650,10 +650,10 @@ void pd_destroy(pd_ctx* c) {
     lg_release(c);
     c->tw.release(); c->twc.release(); c->twf.release(); c->twcf.release();
     c->U.release(); c->Fo.release(); c->Gold.release();
-    c->Hf.release(); c->T1f.release(); c->T2f.release(); c->Uprev.release(); c->t0s.release();
+    c->Hf.release(); c->T1f.release(); c->Uprev.release(); c->t0s.release();
     c->Bc.release(); c->Hc.release(); c->T1c.release(); c->T2c.release(); c->red.release();
     c->ftab.release(); c->Rf.release(); c->Rc.release(); c->wR.release();
-    c->flag.release(); c->wB.release(); c->wH.release(); c->wT1.release(); c->wT2.release();
+    c->flag.release(); c->wB.release(); c->wH.release(); c->wT1.release();
     c->wt0.release();
   }
   delete c;
@@ -748,7 +748,7 @@ pd_status pd_set_precision(pd_ctx* c, pd_prec prec) {
   c->last_k = -1;
   lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
-  c->T2f.release(); c->Uprev.release(); c->Bc.release(); c->Hc.release(); c->T1c.release();
+  c->Uprev.release(); c->Bc.release(); c->Hc.release(); c->T1c.release();
   c->T2c.release();
   c->prec = prec;
   return PD_OK;
@@ -769,7 +769,7 @@ pd_status pd_set_problem(pd_ctx* c, pd_flow flow, double Rm, double kz, int N) {
   c->last_k = -1;
   lg_release(c);
   c->U.release(); c->Fo.release(); c->Gold.release(); c->Hf.release(); c->T1f.release();
-  c->T2f.release(); c->Uprev.release();
+  c->Uprev.release();
   c->rows_v = c->cols_v = -1;
   c->flow = flow;
   c->Rm = Rm;
@@ -817,7 +817,6 @@ pd_status pd_set_time(pd_ctx* c, double T, int P, double dtf, double dtc, int Nc
   PD_HIP(c, c->Gold.ensure(box * P), "alloc Gold");
   PD_HIP(c, c->Hf.ensure(box * P), "alloc H");
   PD_HIP(c, c->T1f.ensure(rows * P), "alloc T1");
-  PD_HIP(c, c->T2f.ensure(rows * P), "alloc T2");
   PD_HIP(c, c->Uprev.ensure(box), "alloc");
   PD_HIP(c, c->Bc.ensure(cbox), "alloc");
   PD_HIP(c, c->Hc.ensure(cbox), "alloc");
@@ -1139,7 +1138,7 @@ pd_status pd_autotune(pd_ctx* c, int reps, const char* cache_path, int* chosen, 
   fb.B = c->Fo.as<cplx>();
   fb.H = c->Hf.as<cplx>();
   fb.T1 = c->T1f.as<cplx>();
-  fb.T2 = c->T2f.as<cplx>();
+  fb.T2 = fb.T1;
   fb.t0 = c->t0s.as<double>();
   fb.tw = c->tw.as<cplx>();
   const pd::Problem pf = make_problem(c, c->dtf);

@@ -99,11 +99,11 @@ def test_default_blocking_and_argument_errors(lib):
         ctx.set_problem("gp", 2000.0, 0.57, 512)
         with pytest.raises(lib.PitdynError):
             ctx.fine_blocking()                   # before pd_set_time
-        ctx.set_time(4.0, 4, 5e-4, 2.5e-3, 64)
-        assert ctx.fine_blocking() == (3, 3)      # default at 512^2
+        ctx.set_time(8.0, 8, 5e-4, 2.5e-3, 64)
+        assert ctx.fine_blocking() == (4, 3)      # default at 512^2
         ctx.set_fine_blocking(0)
         assert ctx.fine_blocking() == OFF
-        ctx.set_fine_blocking(4, 2)
+        ctx.set_fine_blocking(8, 2)
         assert ctx.fine_blocking() == OFF         # a group as large as the batch: unblocked
         for bad in ((-2, 1), (2, 0), (2, 4)):
             with pytest.raises(lib.PitdynError):
@@ -111,7 +111,7 @@ def test_default_blocking_and_argument_errors(lib):
     with lib.Context(0) as ctx:
         ctx.set_problem("gp", 500.0, 0.57, 256)
         ctx.set_time(16.0, 32, 1e-3, 5e-3, 64)
-        assert ctx.fine_blocking() == (16, 2)     # default at 256^2
+        assert ctx.fine_blocking() == (16, 3)     # default at 256^2
     with lib.Context(0) as ctx:
         ctx.set_problem("gp", 100.0, 0.57, 128)
         ctx.set_time(4.0, 4, 2e-3, 1e-2, 64)

@@ -73,7 +73,7 @@ def test_config5_stepwise_sweep_matches_oracle(lib):
         U = ctx.get_slices_dev()
         start = {n: U[n].cpu().numpy() for n in samples}
         del U
-        ctx.set_fine_blocking(3, 3)             # the blocked order (groups of 3 on 3 streams)
+        ctx.set_fine_blocking(4, 3)             # the blocked order (groups of 4 on 3 streams)
         ctx.fine_sweep_steps(0, 2)
         ms = ctx.fine_sweep_steps(2, 1, timed=True)
         assert ms[0] == ms[1] == -1.0 and ms[2] > 0
