@@ -224,6 +224,25 @@ __device__ __forceinline__ void row_phase(int r, bool active, int j, C* s, C* __
 // (pitch TX + 1) so that global loads and stores run along x and all three
 // are in flight at once; once every group holds its column in registers the
 // tile memory doubles as the groups' FFT exchange spans.
+// (cr, sr) = (cos, sin)(theta + 2 pi e / E) from (c, s) = (cos, sin) theta,
+// E = 2, 4 or 8 (e a compile-time index after unrolling): eighth turns are
+// sign swaps, odd ones a scaling by sqrt(1/2).
+template <int E, class Rl>
+__device__ __forceinline__ void turn(int e, Rl c, Rl s, Rl& cr, Rl& sr) {
+  static_assert(E == 2 || E == 4 || E == 8, "turns by eighths");
+  const Rl h = (Rl)0.70710678118654752440;  // sqrt(1/2)
+  switch ((e * (8 / E)) & 7) {
+    case 0: cr = c; sr = s; break;
+    case 1: cr = h * (c - s); sr = h * (s + c); break;
+    case 2: cr = -s; sr = c; break;
+    case 3: cr = -h * (c + s); sr = h * (c - s); break;
+    case 4: cr = -c; sr = -s; break;
+    case 5: cr = h * (s - c); sr = -h * (s + c); break;
+    case 6: cr = s; sr = -c; break;
+    default: cr = h * (c + s); sr = h * (s - c); break;
+  }
+}
+
 template <int N, int E, int LANES, int CH, class C = cplx>
 __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
                                          const C* __restrict__ tw,
@@ -319,12 +338,15 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
     const Rl cx = tw[xa].re, sx = -tw[xa].im;
     const Rl cxp = cx * fcpx - sx * fspx;   // cos(x + px)
     const Rl sxp = sx * fcpx + cx * fspx;   // sin(x + px)
+    // the lane's rows y_m = y_j + 2 pi e / E (m = j + T e): the angle y_j + py
+    // once, then turned by the exact rotations through multiples of 2 pi / E
+    const Rl cj = tw[j].re, sj = -tw[j].im;
+    const Rl cjp = cj * fcpy - sj * fspy;   // cos(y_j + py)
+    const Rl sjp = sj * fcpy + cj * fspy;   // sin(y_j + py)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int m = j + T * e;
-      const Rl cy = tw[m].re, sy = -tw[m].im;
-      const Rl cyp = cy * fcpy - sy * fspy;  // cos(y + py)
-      const Rl syp = sy * fcpy + cy * fspy;  // sin(y + py)
+      Rl cyp, syp;                           // cos, sin(y_m + py)
+      turn<E>(e, cjp, sjp, cyp, syp);
       const Rl ux = famp * cyp, uy = famp * sxp, uz = famp * (cxp + syp);
       const C bx = w[0][e], by = w[1][e], bz = w[2][e];
       w[0][e] = csub(cscale(bz, uy), cscale(by, uz));
