@@ -243,10 +243,11 @@ __device__ __forceinline__ void turn(int e, Rl c, Rl s, Rl& cr, Rl& sr) {
   }
 }
 
-template <int N, int E, int LANES, int CH, class C = cplx>
+// `phase()` gives the flow's phases at the step's time; it is called once
+// the tile's loads are in flight, so its arithmetic overlaps their latency.
+template <int N, int E, int LANES, int CH, class C = cplx, class PhaseFn>
 __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
-                                         const C* __restrict__ tw,
-                                         const FlowPhase& fp) {
+                                         const C* __restrict__ tw, PhaseFn phase) {
   using G = Geo<N, E>;
   using Rl = decltype(C::re);
   constexpr int T = G::T, K = G::K, M = G::M;
@@ -281,6 +282,7 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
   constexpr int NIT = (3 * M + RPL - 1) / RPL;       // passes
   const int cc = tid % TX, R0 = tid / TX;
   const bool cin = x0 + cc < N;
+  FlowPhase fp;
   if constexpr (SW && TX <= 64) {
     // complex128: global memory straight into LDS (global_load_lds, 16
     // bytes a lane): the 64 lanes of wave w fill the 64 consecutive slots
@@ -300,8 +302,10 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
             (lds_void*)(tile + (wbase + it * RPL) * TX), 16, 0, 0);
       }
     }
+    fp = phase();
     __builtin_amdgcn_s_waitcnt(0);
   } else {
+    fp = phase();
     const C* src = T1 + (size_t)R0 * N + x0 + cc;
 #pragma unroll 1
     for (int i0 = 0; i0 < NIT; i0 += CH) {
@@ -561,9 +565,9 @@ __attribute__((amdgpu_waves_per_eu(MINW))) void k_cols(FieldBatchT<C> fb, Proble
   // SBDF steps at t0 + step dt; Runge-Kutta stage `stage` at t0 + step dt + c dt
   const double t = stage == 0 ? fb.t0[f] + step * pb.dt
                               : fb.t0[f] + step * pb.dt + pb.rk_c[stage - 1] * pb.dt;
-  const FlowPhase fp = flow_phase(pb, t);
   col_tile<N, E, TX * G::T, E == 8 ? 8 : 4, C>(xt * TX, tile, fb.T1 + f * rows,
-                                            fb.T2 + f * rows, fb.tw, fp);
+                                            fb.T2 + f * rows, fb.tw,
+                                            [&] { return flow_phase(pb, t); });
 }
 
 // Persistent column phase: a grid sized to the chip's resident workgroups
@@ -703,7 +707,8 @@ __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* 
         constexpr int js = decltype(js_c)::value;
         if (js > pb.rk_s) return;
         const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt + pb.rk_c[js - 1] * pb.dt);
-        for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
+        for (int x0 = 0; x0 < N; x0 += TX)
+          col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, [&] { return fp; });
         const bool last = step == nsteps - 1 && js == pb.rk_s;
         for (int r0 = 0; r0 < M; r0 += NGR)
           row_phase<N, ER, js>(r0 + rg, r0 + rg < M, rj, spans + rg * S::GR::SPAN, B, H, T2, T1,
@@ -718,7 +723,8 @@ __device__ __forceinline__ void propagate_wg(cplx* lds, cplx* B, cplx* H, cplx* 
   } else {
     for (int step = 0; step < nsteps; ++step) {
       const FlowPhase fp = flow_phase(pb, t0 + step * pb.dt);
-      for (int x0 = 0; x0 < N; x0 += TX) col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, fp);
+      for (int x0 = 0; x0 < N; x0 += TX)
+        col_tile<N, EC, S::L, 1>(x0, tile, T1, T2, tw, [&] { return fp; });
       const int mode = step == 0 ? 1 : 2;
       const bool last = step == nsteps - 1;
       for (int r0 = 0; r0 < M; r0 += NGR)
