@@ -243,8 +243,10 @@ __device__ __forceinline__ void turn(int e, Rl c, Rl s, Rl& cr, Rl& sr) {
   }
 }
 
-// `phase()` gives the flow's phases at the step's time; it is called once
-// the tile's loads are in flight, so its arithmetic overlaps their latency.
+// `phase()` gives the flow's phases at the step's time; the first wavefront
+// evaluates it (three double-precision sincos) once the tile's loads are in
+// flight, so its arithmetic overlaps their latency, and leaves it in LDS for
+// the others.
 template <int N, int E, int LANES, int CH, class C = cplx, class PhaseFn>
 __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
                                          const C* __restrict__ tw, PhaseFn phase) {
@@ -282,7 +284,13 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
   constexpr int NIT = (3 * M + RPL - 1) / RPL;       // passes
   const int cc = tid % TX, R0 = tid / TX;
   const bool cin = x0 + cc < N;
-  FlowPhase fp;
+  __shared__ FlowPhase fsh;
+  const auto share_phase = [&] {
+    if (tid < 64) {
+      const FlowPhase f = phase();
+      if (tid == 0) fsh = f;
+    }
+  };
   if constexpr (SW && TX <= 64) {
     // complex128: global memory straight into LDS (global_load_lds, 16
     // bytes a lane): the 64 lanes of wave w fill the 64 consecutive slots
@@ -302,10 +310,10 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
             (lds_void*)(tile + (wbase + it * RPL) * TX), 16, 0, 0);
       }
     }
-    fp = phase();
+    share_phase();
     __builtin_amdgcn_s_waitcnt(0);
   } else {
-    fp = phase();
+    share_phase();
     const C* src = T1 + (size_t)R0 * N + x0 + cc;
 #pragma unroll 1
     for (int i0 = 0; i0 < NIT; i0 += CH) {
@@ -337,6 +345,7 @@ __device__ __forceinline__ void col_tile(int x0, C* tile, const C* T1, C* T2,
     for (int c = 0; c < 3; ++c) fft<N, E, 1>(w[c], s, j, twr);
     // E = u x b at (x, y_e)
     const int xa = active ? x : 0;
+    const FlowPhase fp = fsh;
     const Rl fcpx = (Rl)fp.cpx, fspx = (Rl)fp.spx, fcpy = (Rl)fp.cpy, fspy = (Rl)fp.spy;
     const Rl famp = (Rl)fp.amp;
     const Rl cx = tw[xa].re, sx = -tw[xa].im;
