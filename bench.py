@@ -52,7 +52,7 @@ N5, RM5, T5, P5, DT5, SEED5 = 512, 2000.0, 256.0, 256, 5e-4, 500000
 NC5, DTC5 = 64, 2.5e-3
 ALG_BYTES_PER_MODE_STEP = 192.0    # read + write b and H, 3 x complex128, full grid
 HBM_PEAK_GBS = 8000.0
-CPU_WORKERS_MAX = 16               # a one-GPU machine's share of host cores
+CPU_WORKERS_MAX = 16               # at most a single-GPU host share of its cores
 UNBLOCKED_STEPS = 5                # steps timed kernel by kernel before the blocked sweep
 
 
