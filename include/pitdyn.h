@@ -153,8 +153,8 @@ pd_status pd_set_precision(pd_ctx* ctx, pd_prec prec);
    dT = T/n_slices; fine step dt_fine, coarse step dt_coarse on an N_coarse
    grid (0 = same as N, else a power of two in [16, N]).  dT/dt_fine and
    dT/dt_coarse must be integers to 1e-9 relative.  Allocates the slice buffers
-   ((4 n_slices + 2) fields of 3 (2K+1)^2 complex values plus 2 n_slices row
-   buffers of 3 (2K+1) N values). */
+   ((4 n_slices + 2) fields of 3 (2K+1)^2 complex values plus n_slices row
+   buffers of 3 (2K+1) N values, used in place by both transform phases). */
 pd_status pd_set_time(pd_ctx* ctx, double T, int n_slices, double dt_fine, double dt_coarse,
                       int N_coarse);
 
@@ -281,7 +281,7 @@ pd_status pd_set_pipeline(pd_ctx* ctx, int chunks, int speculate);
    fine steps before the next group on its stream starts, and the groups are
    dealt round-robin to `streams` streams (1..3: the context's stream and the
    two streams of the pipelined schedule, idle outside it), so a group's
-   state, history and row buffers stay in the device's last-level cache
+   state, history and row buffer stay in the device's last-level cache
    across its steps instead of streaming through HBM at every step.
    group = 0: off (every step runs over the whole batch); group = -1
    (default): groups of 4 fields on 3 streams at 512^2, of 16 fields on 3
